@@ -104,6 +104,20 @@ class CSC:
         a, b = self.colptr[j], self.colptr[j + 1]
         return self.rowidx[a:b], self.val[a:b]
 
+    def restrict_columns(self, cols) -> "CSC":
+        """The sub-matrix made of the listed columns (all rows)."""
+        cols = np.asarray(cols, np.int64)
+        cnt = self.colptr[cols + 1] - self.colptr[cols]
+        cp = np.zeros(len(cols) + 1, np.int64)
+        cp[1:] = np.cumsum(cnt)
+        if len(cols):
+            starts = np.repeat(self.colptr[cols], cnt)
+            within = np.arange(int(cp[-1]), dtype=np.int64) - np.repeat(cp[:-1], cnt)
+            idx = starts + within
+        else:
+            idx = np.zeros(0, np.int64)
+        return CSC(self.nrows, len(cols), cp, self.rowidx[idx], self.val[idx])
+
 
 # --------------------------------------------------------------------------
 # cluster sizes

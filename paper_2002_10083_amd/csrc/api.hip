@@ -1,0 +1,969 @@
+// C-ABI entry points (include/mcl.h): argument checks, workspace management
+// through the caller's stream-ordered allocator, and the orchestration of the
+// symbolic / estimate / plan / numeric / fallback / compaction kernels.
+#include "mcl.h"
+#include "internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+#define HIPC(x)                                                                          \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            fail(MCL_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+// Workspace and output memory of one call.  Workspace is released at the end
+// of the call (stream-ordered); outputs are released only on error.
+struct Mem {
+    const mcl_allocator *al;
+    hipStream_t st;
+    std::vector<void *> work, outs;
+    size_t cur = 0, peak = 0;
+    std::vector<size_t> sizes;
+
+    void *raw(size_t bytes)
+    {
+        if (bytes == 0) bytes = 8;
+        void *p = nullptr;
+        if (al && al->alloc) {
+            p = al->alloc(al->ctx, bytes, (void *)st);
+            if (!p) fail(MCL_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMallocAsync(&p, bytes, st);
+            if (e != hipSuccess || !p)
+                fail(MCL_ENOMEM, "hipMallocAsync failed for " + std::to_string(bytes) + " bytes");
+        }
+        return p;
+    }
+    template <typename T>
+    T *ws(int64_t n)
+    {
+        size_t b = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+        void *p = raw(b);
+        work.push_back(p);
+        cur += b;
+        peak = std::max(peak, cur);
+        return (T *)p;
+    }
+    template <typename T>
+    T *out(int64_t n)
+    {
+        size_t b = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+        void *p = raw(b);
+        outs.push_back(p);
+        cur += b;
+        peak = std::max(peak, cur);
+        return (T *)p;
+    }
+    void release(void *p)
+    {
+        if (!p) return;
+        if (al && al->free) al->free(al->ctx, p, (void *)st);
+        else (void)hipFreeAsync(p, st);
+    }
+    void free_work()
+    {
+        for (void *p : work) release(p);
+        work.clear();
+    }
+    void free_outs()
+    {
+        for (void *p : outs) release(p);
+        outs.clear();
+    }
+};
+
+struct Timer {
+    hipStream_t st;
+    std::vector<hipEvent_t> ev;
+    void mark()
+    {
+        hipEvent_t e;
+        if (hipEventCreate(&e) == hipSuccess) {
+            (void)hipEventRecord(e, st);
+            ev.push_back(e);
+        }
+    }
+    double ms(size_t a, size_t b)
+    {
+        if (b >= ev.size() || a >= ev.size()) return 0.0;
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+    ~Timer()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+mcl::DevCSC dev(const mcl_csc &m)
+{
+    return mcl::DevCSC{m.nrows, m.ncols, m.nnz, m.colptr, m.rowidx, m.val};
+}
+
+void check_csc(const mcl_csc *m, const char *name)
+{
+    if (!m) fail(MCL_EINVAL, std::string(name) + " is NULL");
+    if (m->nrows < 0 || m->ncols < 0 || m->nnz < 0)
+        fail(MCL_EINVAL, std::string(name) + ": negative dimension");
+    if (m->nrows >= (int64_t)INT32_MAX || m->ncols >= (int64_t)INT32_MAX)
+        fail(MCL_EINVAL, std::string(name) + ": dimensions must be < 2^31");
+    if (!m->colptr) fail(MCL_EINVAL, std::string(name) + ": colptr is NULL");
+    if (m->nnz > 0 && (!m->rowidx || !m->val))
+        fail(MCL_EINVAL, std::string(name) + ": rowidx/val NULL with nnz > 0");
+}
+
+void validate_dev(Mem &mem, const mcl_csc *m, const char *name)
+{
+    int32_t *flag = mem.ws<int32_t>(1);
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int32_t), mem.st));
+    mcl::launch_validate(dev(*m), flag, mem.st);
+    int32_t h = 0;
+    HIPC(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipStreamSynchronize(mem.st));
+    if (h) fail(MCL_EINVAL, std::string(name) + ": malformed CSC (unsorted/out-of-range rows, "
+                                                 "non-positive or non-finite values, or bad colptr)");
+}
+
+mcl::PruneArgs prune_args(const mcl_params &p)
+{
+    mcl::PruneArgs a;
+    a.theta = p.prune_threshold;
+    a.S = p.select_num;
+    a.R = p.recover_num;
+    a.pct = p.recover_pct;
+    a.r = p.inflation;
+    return a;
+}
+
+void check_params(const mcl_params &p)
+{
+    if (!(p.prune_threshold >= 0.0) || !std::isfinite(p.prune_threshold))
+        fail(MCL_EINVAL, "prune_threshold must be finite and >= 0");
+    if (p.select_num < 0 || p.recover_num < 0) fail(MCL_EINVAL, "select/recover counts must be >= 0");
+    if (!(p.recover_pct >= 0.0 && p.recover_pct <= 1.0)) fail(MCL_EINVAL, "recover_pct must be in [0,1]");
+    if (!(p.inflation > 0.0) || !std::isfinite(p.inflation)) fail(MCL_EINVAL, "inflation must be > 0");
+    if (p.estimator < MCL_EST_BOUND || p.estimator > MCL_EST_MLP) fail(MCL_EINVAL, "unknown estimator");
+    if (p.estimator == MCL_EST_COHEN && (p.cohen_keys < 2 || p.cohen_keys > 16))
+        fail(MCL_EINVAL, "cohen_keys must be in [2,16]");
+    if (p.estimator == MCL_EST_MLP && !p.mlp_weights) fail(MCL_EINVAL, "MLP estimator needs mlp_weights");
+    if (!(p.est_scale > 0.0)) fail(MCL_EINVAL, "est_scale must be > 0");
+}
+
+int64_t next_pow2(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <typename F>
+int guarded(F &&f)
+{
+    try {
+        f();
+        return MCL_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host out of memory";
+        return MCL_ENOMEM;
+    } catch (...) {
+        g_err = "unknown internal error";
+        return MCL_EHIP;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The product engine shared by expand, iterate, symbolic and merge.
+// ---------------------------------------------------------------------------
+struct ProductPlan {
+    // per column (size n)
+    int64_t *flops = nullptr;
+    int32_t *lo = nullptr, *hi = nullptr;
+    float *est = nullptr;
+    int32_t *bin = nullptr;
+    int64_t *capv = nullptr;
+    int64_t *base = nullptr;  // n+1
+    int64_t *cnt = nullptr;
+    int32_t *lists = nullptr;
+    int32_t counts[8] = {0};
+    int64_t max_global = 0;
+    int64_t temp_total = 0;
+};
+
+struct EngineOut {
+    mcl::TempRegions tr{};
+    int nregions = 0;
+    int64_t n_overflow = 0, n_global = 0;
+    double t_numeric = 0, t_fallback = 0;
+    double bin_ms[8] = {0};
+    int64_t bin_cols[8] = {0};
+    int64_t bin_acc[24] = {0};  // per bin: flops, nnz(B_*j), output entries
+};
+
+mcl::BinOffsets offsets_of(const int32_t counts[8])
+{
+    mcl::BinOffsets off{};
+    int32_t run = 0;
+    for (int b = 0; b < 8; ++b) { off.off[b] = run; run += counts[b]; }
+    return off;
+}
+
+// Launch every non-empty bin; per-bin times are accumulated into eo.bin_ms
+// when `timed` (events around each launch, on the stream).
+void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t counts[8],
+              const int32_t *lists, int64_t max_global, EngineOut &eo, bool timed, uint32_t policy = 0)
+{
+    int32_t off = 0;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> evbin;
+    for (int b = 0; b < 8; ++b) {
+        const int32_t c = counts[b];
+        if (c > 0) {
+            a.cols = lists + off;
+            a.ncols = c;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                HIPC(hipEventCreate(&e0));
+                HIPC(hipEventCreate(&e1));
+                HIPC(hipEventRecord(e0, mem.st));
+            }
+            if (b < mcl::NUM_LDS_BINS) {
+                int variant = (int)((policy >> (4 * b)) & 15u);
+                if (variant >= mcl::lds_bin_variants(b)) variant = 0;
+                mcl::launch_numeric_lds(b, variant, mode, a, mem.st);
+            } else {
+                const int64_t S = next_pow2((max_global * 4) / 3 + 2);
+                if (S > (int64_t)1 << 30) fail(MCL_EINVAL, "product column too large for the HBM table");
+                const int cap = (int)std::min<int64_t>((S * 3) / 4, max_global);
+                const size_t slab = mcl::global_slab_bytes((int)S, (int)std::max<int64_t>(cap, 1));
+                const size_t budget = (size_t)4 << 30;
+                int nslabs = (int)std::max<size_t>(1, std::min<size_t>(budget / slab, 1024));
+                nslabs = std::min(nslabs, c);
+                char *sl = mem.ws<char>((int64_t)(slab * nslabs));
+                mcl::launch_numeric_global(mode, a, (int)S, cap, sl, slab, nslabs, mem.st);
+                eo.n_global += c;
+            }
+            HIPC(hipGetLastError());
+            if (timed) {
+                HIPC(hipEventRecord(e1, mem.st));
+                ev.push_back(e0);
+                ev.push_back(e1);
+                evbin.push_back(b);
+            }
+            eo.bin_cols[b] += c;
+        }
+        off += c;
+    }
+    if (timed && !ev.empty()) {
+        HIPC(hipEventSynchronize(ev.back()));
+        for (size_t i = 0; i < evbin.size(); ++i) {
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            eo.bin_ms[evbin[i]] += t;
+        }
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+}
+
+// Runs the numeric phase for the columns binned in `pl`, then resolves table
+// overflow: overflowed columns move one LDS bin up and are recomputed into a
+// new temp region; columns that overflow the largest LDS bin get an exact
+// count and the HBM table.  `a` carries A/B (or parts), the prune args and
+// the per-column outputs.
+void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::NumericArgs a,
+            ProductPlan &pl, EngineOut &eo, Timer &tm, const int64_t *bcolptr = nullptr,
+            uint32_t policy = 0)
+{
+    int32_t *trow = mem.ws<int32_t>(pl.temp_total);
+    double *tval = (mode == mcl::MODE_COUNT) ? nullptr : mem.ws<double>(pl.temp_total);
+    eo.tr.row[0] = trow;
+    eo.tr.val[0] = tval;
+    eo.nregions = 1;
+    {
+        mcl::BinOffsets off = offsets_of(pl.counts);
+        int32_t *cursor = mem.ws<int32_t>(8);
+        HIPC(hipMemsetAsync(cursor, 0, 8 * sizeof(int32_t), mem.st));
+        mcl::launch_scatter_bins(n, pl.bin, off, cursor, pl.lists, mem.st);
+    }
+    {
+        int64_t *dummy = mem.ws<int64_t>(8);
+        HIPC(hipMemsetAsync(dummy, 0, 8 * sizeof(int64_t), mem.st));
+        a.dummy = dummy;
+    }
+    a.lo = pl.lo;
+    a.hi = pl.hi;
+    a.out_base = pl.base;
+    a.capv = pl.capv;
+    a.out_row = trow;
+    a.out_val = tval;
+    a.out_cnt = pl.cnt;
+    tm.mark();
+    const size_t t0 = tm.ev.size() - 1;
+    run_bins(mem, mode, a, pl.counts, pl.lists, pl.max_global, eo, true, policy);
+    // per-bin totals of the first pass (the launch shape the timing refers to)
+    {
+        int64_t *acc = mem.ws<int64_t>(24);
+        HIPC(hipMemsetAsync(acc, 0, 24 * sizeof(int64_t), mem.st));
+        mcl::BinOffsets cnt{};
+        for (int b = 0; b < 8; ++b) cnt.off[b] = pl.counts[b];
+        mcl::launch_bin_sums(pl.lists, offsets_of(pl.counts), cnt, pl.flops, bcolptr, pl.cnt, acc, mem.st);
+        HIPC(hipMemcpyAsync(eo.bin_acc, acc, sizeof(eo.bin_acc), hipMemcpyDeviceToHost, mem.st));
+    }
+    tm.mark();
+    const size_t t1 = tm.ev.size() - 1;
+
+    const int32_t *cur_list = pl.lists;
+    int32_t cur_n = 0;
+    for (int b = 0; b < 8; ++b) cur_n += pl.counts[b];
+    int32_t *ovf = mem.ws<int32_t>(std::max<int32_t>(cur_n, 1));
+    int32_t *dev_i = mem.ws<int32_t>(16);
+    int64_t *dev_l = mem.ws<int64_t>(4);
+    int64_t *ub = nullptr;
+    for (int round = 1;; ++round) {
+        HIPC(hipMemsetAsync(dev_i, 0, 16 * sizeof(int32_t), mem.st));
+        mcl::launch_collect_overflow(n, cur_list, cur_n, pl.cnt, ovf, dev_i, mem.st);
+        int32_t novf = 0;
+        HIPC(hipMemcpyAsync(&novf, dev_i, sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        if (round == 1) eo.t_numeric = tm.ms(t0, t1);
+        if (novf == 0) break;
+        if (round == 1) eo.n_overflow = novf;
+        if (round >= mcl::MAX_REGIONS) fail(MCL_EHIP, "table overflow did not resolve");
+        // bump one bin up; the largest LDS bin goes to the exact path
+        int32_t *counts_d = dev_i + 1;       // 8 counters
+        int32_t *nexact_d = dev_i + 9;
+        int32_t *exact = mem.ws<int32_t>(novf);
+        mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d, mem.st);
+        int32_t hc[9];
+        HIPC(hipMemcpyAsync(hc, counts_d, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        int32_t counts2[8];
+        for (int b = 0; b < 8; ++b) counts2[b] = hc[b];
+        const int32_t nexact = hc[8];
+        int64_t max_need = 0;
+        if (nexact > 0) {
+            // exact product size with an exact-safe HBM table, then bin 7
+            if (!ub) ub = mem.ws<int64_t>(n);
+            HIPC(hipMemsetAsync(dev_l, 0, 4 * sizeof(int64_t), mem.st));
+            mcl::launch_list_bound(exact, nexact, pl.flops, pl.lo, pl.hi, nrows, ub, dev_l, mem.st);
+            int64_t max_ub = 0;
+            HIPC(hipMemcpyAsync(&max_ub, dev_l, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipStreamSynchronize(mem.st));
+            mcl::NumericArgs c = a;
+            c.capv = nullptr;
+            c.out_row = nullptr;
+            c.out_val = nullptr;
+            int32_t cc[8] = {0, 0, 0, 0, 0, 0, 0, nexact};
+            EngineOut dummy;
+            run_bins(mem, mcl::MODE_COUNT, c, cc, exact, std::max<int64_t>(max_ub, 1), dummy, false);
+            HIPC(hipMemsetAsync(dev_i + 10, 0, 6 * sizeof(int32_t), mem.st));
+            HIPC(hipMemsetAsync(dev_l, 0, 4 * sizeof(int64_t), mem.st));
+            int32_t *bc2 = mem.ws<int32_t>(8);
+            HIPC(hipMemsetAsync(bc2, 0, 8 * sizeof(int32_t), mem.st));
+            mcl::launch_replan(exact, nexact, pl.cnt, pl.bin, pl.capv, bc2, dev_l, mem.st);
+            int32_t hb2[8];
+            HIPC(hipMemcpyAsync(hb2, bc2, sizeof(hb2), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipMemcpyAsync(&max_need, dev_l, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipStreamSynchronize(mem.st));
+            for (int b = 0; b < 8; ++b) counts2[b] += hb2[b];
+        }
+        // new temp region for the recomputed columns
+        const int region = eo.nregions;
+        mcl::launch_list_base(ovf, novf, pl.capv, pl.base, dev_l + 1, region, mem.st);
+        int64_t rtotal = 0;
+        HIPC(hipMemcpyAsync(&rtotal, dev_l + 1, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        int32_t *rrow = mem.ws<int32_t>(rtotal);
+        double *rval = (mode == mcl::MODE_COUNT) ? nullptr : mem.ws<double>(rtotal);
+        eo.tr.row[region] = rrow;
+        eo.tr.val[region] = rval;
+        eo.nregions = region + 1;
+        int32_t *lists2 = mem.ws<int32_t>(novf);
+        {
+            int32_t *cursor = mem.ws<int32_t>(8);
+            HIPC(hipMemsetAsync(cursor, 0, 8 * sizeof(int32_t), mem.st));
+            mcl::launch_scatter_bins_list(ovf, novf, pl.bin, offsets_of(counts2), cursor, lists2, mem.st);
+        }
+        a.out_row = rrow;
+        a.out_val = rval;
+        run_bins(mem, mode, a, counts2, lists2, std::max<int64_t>(max_need, 1), eo, false, policy);
+        // the next round inspects only the recomputed columns
+        int32_t *next = mem.ws<int32_t>(novf);
+        HIPC(hipMemcpyAsync(next, lists2, novf * sizeof(int32_t), hipMemcpyDeviceToDevice, mem.st));
+        cur_list = next;
+        cur_n = novf;
+    }
+    tm.mark();
+    HIPC(hipStreamSynchronize(mem.st));
+    eo.t_fallback = tm.ms(t1, tm.ev.size() - 1);
+}
+
+void copy_bin_stats(const EngineOut &eo, mcl_stats *s)
+{
+    if (!s) return;
+    for (int b = 0; b < 8; ++b) {
+        s->bin_cols[b] = eo.bin_cols[b];
+        s->bin_ms[b] = eo.bin_ms[b];
+        s->bin_flops[b] = eo.bin_acc[3 * b];
+        s->bin_bnnz[b] = eo.bin_acc[3 * b + 1];
+        s->bin_out[b] = eo.bin_acc[3 * b + 2];
+    }
+}
+
+// Symbolic pass + estimate + plan for C = A*B (or the merge of parts).
+void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mcl_params &p,
+                  const uint8_t *col_active, ProductPlan &pl, Timer &tm, double *t_sym,
+                  double *t_est, float *feat_out)
+{
+    const int64_t n = B.ncols;
+    pl.flops = mem.ws<int64_t>(n);
+    pl.lo = mem.ws<int32_t>(n);
+    pl.hi = mem.ws<int32_t>(n);
+    pl.est = mem.ws<float>(n);
+    pl.bin = mem.ws<int32_t>(n);
+    pl.capv = mem.ws<int64_t>(n + 1);
+    pl.base = mem.ws<int64_t>(n + 1);
+    pl.cnt = mem.ws<int64_t>(n);
+    pl.lists = mem.ws<int32_t>(n);
+    tm.mark();
+    const size_t e0 = tm.ev.size() - 1;
+    const float *colmin = nullptr;
+    const int r = p.cohen_keys;
+    if (p.estimator == MCL_EST_COHEN) {
+        float *keys = mem.ws<float>(A.nrows * r);
+        float *cm = mem.ws<float>(A.ncols * r);
+        mcl::launch_cohen_keys(A.nrows, r, p.seed, p.iteration, keys, mem.st);
+        mcl::launch_cohen_colmin(A, keys, r, cm, mem.st);
+        colmin = cm;
+    }
+    float *feat = feat_out;
+    if (p.estimator == MCL_EST_MLP && !feat) feat = mem.ws<float>(n * 12);
+    mcl::launch_symbolic(A, B, pl.flops, pl.lo, pl.hi, colmin, r, colmin ? pl.est : nullptr, feat,
+                         nullptr, p.iteration, mem.st);
+    tm.mark();
+    const size_t e1 = tm.ev.size() - 1;
+    if (p.estimator == MCL_EST_MLP) {
+        mcl::launch_mlp_forward(p.mlp_weights, feat, n, pl.est, mem.st);
+        mcl::launch_expm1_inplace(pl.est, n, mem.st);
+    }
+    if (p.est_out && p.estimator != MCL_EST_BOUND)
+        HIPC(hipMemcpyAsync(p.est_out, pl.est, n * sizeof(float), hipMemcpyDeviceToDevice, mem.st));
+    tm.mark();
+    const size_t e2 = tm.ev.size() - 1;
+    int32_t *bc = mem.ws<int32_t>(8);
+    int64_t *mg = mem.ws<int64_t>(1);
+    HIPC(hipMemsetAsync(bc, 0, 8 * sizeof(int32_t), mem.st));
+    HIPC(hipMemsetAsync(mg, 0, sizeof(int64_t), mem.st));
+    mcl::launch_plan(n, pl.flops, pl.lo, pl.hi, pl.est, p.estimator, p.est_scale, A.nrows, col_active,
+                     pl.bin, pl.capv, bc, mg, mem.st);
+    int64_t *tmp = mem.ws<int64_t>(mcl::exscan_tmp_elems(n));
+    mcl::launch_exscan_i64(pl.capv, pl.base, n, tmp, mem.st);
+    HIPC(hipMemcpyAsync(pl.counts, bc, sizeof(pl.counts), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipMemcpyAsync(&pl.max_global, mg, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipMemcpyAsync(&pl.temp_total, pl.base + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipStreamSynchronize(mem.st));
+    if (t_sym) *t_sym = tm.ms(e0, e1);
+    if (t_est) *t_est = tm.ms(e1, e2);
+}
+
+// colptr = exclusive scan of cnt; returns nnz (host).
+int64_t scan_counts(Mem &mem, const int64_t *cnt, int64_t n, int64_t *colptr)
+{
+    int64_t *tmp = mem.ws<int64_t>(mcl::exscan_tmp_elems(n));
+    mcl::launch_exscan_i64(cnt, colptr, n, tmp, mem.st);
+    int64_t nnz = 0;
+    HIPC(hipMemcpyAsync(&nnz, colptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipStreamSynchronize(mem.st));
+    return nnz;
+}
+
+void zero_out(mcl_csc *C)
+{
+    if (C) {
+        int64_t r = C->nrows, c = C->ncols;
+        std::memset(C, 0, sizeof(*C));
+        C->nrows = r;
+        C->ncols = c;
+    }
+}
+
+template <typename F>
+int with_mem(const mcl_allocator *al, void *stream, mcl_csc *out, F &&f)
+{
+    Mem mem{al, (hipStream_t)stream};
+    int rc = guarded([&] { f(mem); });
+    if (rc != MCL_OK) {
+        (void)hipStreamSynchronize(mem.st);
+        mem.free_outs();
+        zero_out(out);
+    }
+    mem.free_work();
+    if (rc != MCL_OK) (void)hipStreamSynchronize(mem.st);
+    return rc;
+}
+
+void fill_stats_totals(Mem &mem, int64_t n, const int64_t *nnz_prod, const int8_t *mode,
+                       const double *delta, const int64_t *flops, mcl_stats *s, double *dmax_out)
+{
+    int64_t *acc = mem.ws<int64_t>(4);
+    double *dm = mem.ws<double>(1);
+    HIPC(hipMemsetAsync(acc, 0, 4 * sizeof(int64_t), mem.st));
+    HIPC(hipMemsetAsync(dm, 0, sizeof(double), mem.st));
+    mcl::launch_reduce_stats(n, nnz_prod, mode, delta, flops, acc, dm, mem.st);
+    int64_t h[4];
+    double hd = 0.0;
+    HIPC(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipMemcpyAsync(&hd, dm, sizeof(double), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipStreamSynchronize(mem.st));
+    if (s) {
+        if (nnz_prod) s->nnz_product = h[0];
+        s->n_selected = h[1];
+        s->n_recovered = h[2];
+        s->flops = h[3];
+        s->max_change = hd;
+    }
+    if (dmax_out) *dmax_out = hd;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported C ABI
+// ===========================================================================
+extern "C" {
+
+const char *mcl_last_error(void) { return g_err.c_str(); }
+
+void mcl_default_params(mcl_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->prune_threshold = 1e-4;
+    p->select_num = 1100;
+    p->recover_num = 1400;
+    p->recover_pct = 0.9;
+    p->inflation = 2.0;
+    p->estimator = MCL_EST_COHEN;
+    p->cohen_keys = 5;
+    p->seed = 0;
+    p->iteration = 0;
+    p->est_scale = 1.0;
+}
+
+int mcl_normalize(mcl_csc *A, void *stream)
+{
+    return guarded([&] {
+        check_csc(A, "A");
+        mcl::launch_normalize(A->ncols, A->colptr, A->val, (hipStream_t)stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+int mcl_expand(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, const mcl_params *params,
+               const mcl_allocator *alloc, void *stream, mcl_stats *stats)
+{
+    mcl_params p;
+    mcl_default_params(&p);
+    if (params) p = *params;
+    return with_mem(alloc, stream, C, [&](Mem &mem) {
+        if (!C) fail(MCL_EINVAL, "C is NULL");
+        check_csc(A, "A");
+        check_csc(B, "B");
+        check_params(p);
+        if (A->ncols != B->nrows) fail(MCL_EINVAL, "A.ncols != B.nrows");
+        if (p.validate) { validate_dev(mem, A, "A"); validate_dev(mem, B, "B"); }
+        Timer tm{mem.st};
+        tm.mark();
+        const int64_t n = B->ncols;
+        const mcl::DevCSC dA = dev(*A), dB = dev(*B);
+        ProductPlan pl;
+        double tsym = 0, test = 0;
+        plan_product(mem, dA, dB, p, nullptr, pl, tm, &tsym, &test, nullptr);
+        mcl::NumericArgs a{};
+        a.A = dA;
+        a.B = dB;
+        a.pa = prune_args(p);
+        EngineOut eo;
+        engine(mem, n, A->nrows, mcl::MODE_EXPAND, a, pl, eo, tm, B->colptr, (uint32_t)p.bin_policy);
+        if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, pl.cnt, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+        tm.mark();
+        const size_t c0 = tm.ev.size() - 1;
+        int64_t *colptr = mem.out<int64_t>(n + 1);
+        const int64_t nnz = scan_counts(mem, pl.cnt, n, colptr);
+        int32_t *row = mem.out<int32_t>(nnz);
+        double *val = mem.out<double>(nnz);
+        mcl::launch_compact(n, nullptr, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        HIPC(hipGetLastError());
+        tm.mark();
+        fill_stats_totals(mem, n, nullptr, nullptr, nullptr, pl.flops, stats, nullptr);
+        copy_bin_stats(eo, stats);
+        C->nrows = A->nrows;
+        C->ncols = n;
+        C->nnz = nnz;
+        C->colptr = colptr;
+        C->rowidx = row;
+        C->val = val;
+        if (stats) {
+            stats->nnz_product = nnz;
+            stats->nnz_kept = nnz;
+            stats->n_overflow = eo.n_overflow;
+            stats->n_global = eo.n_global;
+            stats->t_symbolic_ms = tsym;
+            stats->t_estimate_ms = test;
+            stats->t_numeric_ms = eo.t_numeric;
+            stats->t_fallback_ms = eo.t_fallback;
+            stats->t_compact_ms = tm.ms(c0, tm.ev.size() - 1);
+            stats->t_total_ms = tm.ms(0, tm.ev.size() - 1);
+            stats->peak_workspace_bytes = (int64_t)mem.peak;
+        }
+    });
+}
+
+int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int64_t ncomp,
+                const uint8_t *active, const mcl_params *params, const mcl_allocator *alloc,
+                void *stream, mcl_stats *stats, double *max_change)
+{
+    mcl_params p;
+    mcl_default_params(&p);
+    if (params) p = *params;
+    return with_mem(alloc, stream, A_next, [&](Mem &mem) {
+        if (!A_next) fail(MCL_EINVAL, "A_next is NULL");
+        check_csc(A, "A");
+        check_params(p);
+        if (A->nrows != A->ncols) fail(MCL_EINVAL, "mcl_iterate needs a square matrix");
+        if (comp_ptr && ncomp <= 0) fail(MCL_EINVAL, "ncomp must be > 0 with comp_ptr");
+        if (comp_ptr && !active) fail(MCL_EINVAL, "active is NULL");
+        if (p.validate) validate_dev(mem, A, "A");
+        Timer tm{mem.st};
+        tm.mark();
+        const int64_t n = A->ncols;
+        const mcl::DevCSC dA = dev(*A);
+        int32_t *col_comp = nullptr;
+        uint8_t *col_active = nullptr;
+        if (comp_ptr) {
+            col_comp = mem.ws<int32_t>(n);
+            col_active = mem.ws<uint8_t>(n);
+            mcl::launch_col_comp(n, comp_ptr, ncomp, col_comp, active, col_active, mem.st);
+        }
+        ProductPlan pl;
+        double tsym = 0, test = 0;
+        plan_product(mem, dA, dA, p, col_active, pl, tm, &tsym, &test, nullptr);
+        int64_t *nnzp = mem.ws<int64_t>(n);
+        double *delta = mem.ws<double>(n);
+        int8_t *mode = mem.ws<int8_t>(n);
+        HIPC(hipMemsetAsync(nnzp, 0, n * sizeof(int64_t), mem.st));
+        HIPC(hipMemsetAsync(mode, 0, n * sizeof(int8_t), mem.st));
+        mcl::NumericArgs a{};
+        a.A = dA;
+        a.B = dA;
+        a.pa = prune_args(p);
+        a.nnz_prod = nnzp;
+        a.delta = delta;
+        a.mode = mode;
+        EngineOut eo;
+        engine(mem, n, A->nrows, mcl::MODE_ITERATE, a, pl, eo, tm, A->colptr, (uint32_t)p.bin_policy);
+        if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);
+        if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, nnzp, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+        tm.mark();
+        const size_t c0 = tm.ev.size() - 1;
+        int64_t *colptr = mem.out<int64_t>(n + 1);
+        const int64_t nnz = scan_counts(mem, pl.cnt, n, colptr);
+        int32_t *row = mem.out<int32_t>(nnz);
+        double *val = mem.out<double>(nnz);
+        mcl::launch_compact(n, pl.bin, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        if (comp_ptr) mcl::launch_copy_inactive(dA, col_comp, active, colptr, row, val, mem.st);
+        HIPC(hipGetLastError());
+        tm.mark();
+        double dmax = 0.0;
+        fill_stats_totals(mem, n, nnzp, mode, delta, pl.flops, stats, &dmax);
+        copy_bin_stats(eo, stats);
+        if (max_change) {
+            if (comp_ptr) {
+                double *cm = mem.ws<double>(ncomp);
+                mcl::launch_comp_max(ncomp, comp_ptr, delta, cm, mem.st);
+                HIPC(hipMemcpyAsync(max_change, cm, ncomp * sizeof(double), hipMemcpyDeviceToHost, mem.st));
+                HIPC(hipStreamSynchronize(mem.st));
+            } else {
+                *max_change = dmax;
+            }
+        }
+        A_next->nrows = A->nrows;
+        A_next->ncols = n;
+        A_next->nnz = nnz;
+        A_next->colptr = colptr;
+        A_next->rowidx = row;
+        A_next->val = val;
+        if (stats) {
+            stats->nnz_kept = nnz;
+            stats->n_overflow = eo.n_overflow;
+            stats->n_global = eo.n_global;
+            stats->t_symbolic_ms = tsym;
+            stats->t_estimate_ms = test;
+            stats->t_numeric_ms = eo.t_numeric;
+            stats->t_fallback_ms = eo.t_fallback;
+            stats->t_compact_ms = tm.ms(c0, tm.ev.size() - 1);
+            stats->t_total_ms = tm.ms(0, tm.ev.size() - 1);
+            stats->peak_workspace_bytes = (int64_t)mem.peak;
+        }
+    });
+}
+
+int mcl_prune(const mcl_csc *B, mcl_csc *C, const mcl_params *params, const mcl_allocator *alloc,
+              void *stream, mcl_stats *stats)
+{
+    mcl_params p;
+    mcl_default_params(&p);
+    if (params) p = *params;
+    return with_mem(alloc, stream, C, [&](Mem &mem) {
+        if (!C) fail(MCL_EINVAL, "C is NULL");
+        check_csc(B, "B");
+        check_params(p);
+        if (p.validate) validate_dev(mem, B, "B");
+        Timer tm{mem.st};
+        tm.mark();
+        const int64_t n = B->ncols;
+        const mcl::DevCSC dB = dev(*B);
+        double *thr = mem.ws<double>(n);
+        int64_t *kept = mem.ws<int64_t>(n);
+        int8_t *mode = mem.ws<int8_t>(n);
+        mcl::launch_prune_plan(dB, prune_args(p), thr, kept, mode, mem.st);
+        int64_t *colptr = mem.out<int64_t>(n + 1);
+        const int64_t nnz = scan_counts(mem, kept, n, colptr);
+        int32_t *row = mem.out<int32_t>(nnz);
+        double *val = mem.out<double>(nnz);
+        mcl::launch_prune_fill(dB, thr, colptr, row, val, mem.st);
+        HIPC(hipGetLastError());
+        tm.mark();
+        fill_stats_totals(mem, n, nullptr, mode, nullptr, nullptr, stats, nullptr);
+        C->nrows = B->nrows;
+        C->ncols = n;
+        C->nnz = nnz;
+        C->colptr = colptr;
+        C->rowidx = row;
+        C->val = val;
+        if (stats) {
+            stats->nnz_product = B->nnz;
+            stats->nnz_kept = nnz;
+            stats->flops = 0;
+            stats->t_total_ms = tm.ms(0, 1);
+            stats->peak_workspace_bytes = (int64_t)mem.peak;
+        }
+    });
+}
+
+int mcl_inflate(mcl_csc *C, double r, void *stream, double *colsum_err_max)
+{
+    Mem mem{nullptr, (hipStream_t)stream};
+    int rc = guarded([&] {
+        check_csc(C, "C");
+        if (!(r > 0.0) || !std::isfinite(r)) fail(MCL_EINVAL, "inflation must be > 0");
+        double *err = nullptr;
+        if (colsum_err_max) {
+            err = mem.ws<double>(1);
+            HIPC(hipMemsetAsync(err, 0, sizeof(double), mem.st));
+        }
+        mcl::launch_inflate(C->ncols, C->colptr, C->val, r, err, mem.st);
+        HIPC(hipGetLastError());
+        if (err) HIPC(hipMemcpyAsync(colsum_err_max, err, sizeof(double), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+    });
+    mem.free_work();
+    return rc;
+}
+
+int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const mcl_allocator *alloc,
+                       void *stream, mcl_stats *stats)
+{
+    return with_mem(alloc, stream, C, [&](Mem &mem) {
+        if (!C) fail(MCL_EINVAL, "C is NULL");
+        if (!parts || nparts <= 0) fail(MCL_EINVAL, "need at least one part");
+        for (int l = 0; l < nparts; ++l) {
+            check_csc(&parts[l], "part");
+            if (parts[l].nrows != parts[0].nrows || parts[l].ncols != parts[0].ncols)
+                fail(MCL_EINVAL, "parts must have the same shape");
+        }
+        Timer tm{mem.st};
+        tm.mark();
+        const int64_t n = parts[0].ncols, nrows = parts[0].nrows;
+        std::vector<mcl::DevCSC> h(nparts);
+        for (int l = 0; l < nparts; ++l) h[l] = dev(parts[l]);
+        mcl::DevCSC *dparts = mem.ws<mcl::DevCSC>(nparts);
+        HIPC(hipMemcpyAsync(dparts, h.data(), nparts * sizeof(mcl::DevCSC), hipMemcpyHostToDevice, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        ProductPlan pl;
+        pl.flops = mem.ws<int64_t>(n);
+        pl.lo = mem.ws<int32_t>(n);
+        pl.hi = mem.ws<int32_t>(n);
+        pl.bin = mem.ws<int32_t>(n);
+        pl.capv = mem.ws<int64_t>(n + 1);
+        pl.base = mem.ws<int64_t>(n + 1);
+        pl.cnt = mem.ws<int64_t>(n);
+        pl.lists = mem.ws<int32_t>(n);
+        mcl::launch_merge_plan(dparts, nparts, n, pl.flops, pl.lo, pl.hi, mem.st);
+        int32_t *bc = mem.ws<int32_t>(8);
+        int64_t *mg = mem.ws<int64_t>(1);
+        HIPC(hipMemsetAsync(bc, 0, 8 * sizeof(int32_t), mem.st));
+        HIPC(hipMemsetAsync(mg, 0, sizeof(int64_t), mem.st));
+        mcl::launch_plan(n, pl.flops, pl.lo, pl.hi, nullptr, MCL_EST_BOUND, 1.0, nrows, nullptr, pl.bin,
+                         pl.capv, bc, mg, mem.st);
+        int64_t *tmp = mem.ws<int64_t>(mcl::exscan_tmp_elems(n));
+        mcl::launch_exscan_i64(pl.capv, pl.base, n, tmp, mem.st);
+        HIPC(hipMemcpyAsync(pl.counts, bc, sizeof(pl.counts), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipMemcpyAsync(&pl.max_global, mg, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipMemcpyAsync(&pl.temp_total, pl.base + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        mcl::NumericArgs a{};
+        a.parts = dparts;
+        a.nparts = nparts;
+        a.A.nrows = nrows;
+        EngineOut eo;
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        engine(mem, n, nrows, mcl::MODE_EXPAND, a, pl, eo, tm);
+        int64_t *colptr = mem.out<int64_t>(n + 1);
+        const int64_t nnz = scan_counts(mem, pl.cnt, n, colptr);
+        int32_t *row = mem.out<int32_t>(nnz);
+        double *val = mem.out<double>(nnz);
+        mcl::launch_compact(n, nullptr, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        HIPC(hipGetLastError());
+        tm.mark();
+        HIPC(hipStreamSynchronize(mem.st));
+        copy_bin_stats(eo, stats);
+        C->nrows = nrows;
+        C->ncols = n;
+        C->nnz = nnz;
+        C->colptr = colptr;
+        C->rowidx = row;
+        C->val = val;
+        if (stats) {
+            stats->nnz_product = nnz;
+            stats->nnz_kept = nnz;
+            stats->n_overflow = eo.n_overflow;
+            stats->n_global = eo.n_global;
+            stats->t_merge_ms = tm.ms(0, tm.ev.size() - 1);
+            stats->t_total_ms = stats->t_merge_ms;
+            stats->peak_workspace_bytes = (int64_t)mem.peak;
+        }
+    });
+}
+
+int mcl_symbolic(const mcl_csc *A, const mcl_csc *B, int64_t *flops_per_col, int64_t *nnz_per_col,
+                 const mcl_allocator *alloc, void *stream)
+{
+    return with_mem(alloc, stream, nullptr, [&](Mem &mem) {
+        check_csc(A, "A");
+        check_csc(B, "B");
+        if (A->ncols != B->nrows) fail(MCL_EINVAL, "A.ncols != B.nrows");
+        if (!flops_per_col) fail(MCL_EINVAL, "flops_per_col is NULL");
+        mcl_params p;
+        mcl_default_params(&p);
+        p.estimator = MCL_EST_BOUND;
+        Timer tm{mem.st};
+        const int64_t n = B->ncols;
+        const mcl::DevCSC dA = dev(*A), dB = dev(*B);
+        ProductPlan pl;
+        plan_product(mem, dA, dB, p, nullptr, pl, tm, nullptr, nullptr, nullptr);
+        HIPC(hipMemcpyAsync(flops_per_col, pl.flops, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+        if (nnz_per_col) {
+            mcl::NumericArgs a{};
+            a.A = dA;
+            a.B = dB;
+            EngineOut eo;
+            engine(mem, n, A->nrows, mcl::MODE_COUNT, a, pl, eo, tm);
+            HIPC(hipMemcpyAsync(nnz_per_col, pl.cnt, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+        }
+        HIPC(hipStreamSynchronize(mem.st));
+    });
+}
+
+int mcl_estimate(const mcl_csc *A, const mcl_csc *B, const mcl_params *params, float *est,
+                 float *features, const mcl_allocator *alloc, void *stream)
+{
+    mcl_params p;
+    mcl_default_params(&p);
+    if (params) p = *params;
+    return with_mem(alloc, stream, nullptr, [&](Mem &mem) {
+        check_csc(A, "A");
+        check_csc(B, "B");
+        check_params(p);
+        if (A->ncols != B->nrows) fail(MCL_EINVAL, "A.ncols != B.nrows");
+        if (!est) fail(MCL_EINVAL, "est is NULL");
+        Timer tm{mem.st};
+        const int64_t n = B->ncols;
+        const mcl::DevCSC dA = dev(*A), dB = dev(*B);
+        p.est_out = est;
+        ProductPlan pl;
+        plan_product(mem, dA, dB, p, nullptr, pl, tm, nullptr, nullptr, features);
+        if (p.estimator == MCL_EST_BOUND) mcl::launch_bound_estimate(n, pl.flops, pl.lo, pl.hi, A->nrows, est, mem.st);
+        HIPC(hipStreamSynchronize(mem.st));
+    });
+}
+
+size_t mcl_mlp_packed_bytes(void) { return mcl::mlp_packed_bytes(); }
+size_t mcl_mlp_state_floats(void) { return mcl::mlp_state_floats(); }
+
+int mcl_mlp_forward(const void *weights, const float *feat, int64_t rows, float *out, void *stream)
+{
+    return guarded([&] {
+        if (!weights || (rows > 0 && (!feat || !out))) fail(MCL_EINVAL, "NULL argument");
+        if (rows < 0) fail(MCL_EINVAL, "rows < 0");
+        mcl::launch_mlp_forward(weights, feat, rows, out, (hipStream_t)stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+int mcl_mlp_init(float *state, uint64_t seed, void *stream)
+{
+    return guarded([&] {
+        if (!state) fail(MCL_EINVAL, "state is NULL");
+        mcl::launch_mlp_init(state, seed, (hipStream_t)stream);
+        HIPC(hipGetLastError());
+        HIPC(hipStreamSynchronize((hipStream_t)stream));
+    });
+}
+
+int mcl_mlp_train_step(float *state, void *packed, const float *feat, const float *target, int64_t rows,
+                       float lr, float *loss, float *grad_out, void *stream)
+{
+    Mem mem{nullptr, (hipStream_t)stream};
+    int rc = guarded([&] {
+        if (!state || !packed || !feat || !target) fail(MCL_EINVAL, "NULL argument");
+        if (rows <= 0) fail(MCL_EINVAL, "rows must be > 0");
+        float *tmp = mem.ws<float>((int64_t)mcl::mlp_train_tmp_floats(rows));
+        mcl::launch_mlp_train_step(state, packed, feat, target, rows, lr, tmp, grad_out, tmp + 1,
+                                   mem.st);
+        HIPC(hipGetLastError());
+        if (loss) HIPC(hipMemcpyAsync(loss, tmp, sizeof(float), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+    });
+    mem.free_work();
+    if (rc != MCL_OK) (void)hipStreamSynchronize((hipStream_t)stream);
+    return rc;
+}
+
+}  // extern "C"

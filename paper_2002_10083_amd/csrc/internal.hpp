@@ -1,0 +1,135 @@
+// Host-side interface between the C-ABI layer (api.hip) and the kernel
+// launchers (spgemm.hip, prune.hip, merge.hip, mlp.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcl {
+
+struct DevCSC {
+    int64_t nrows, ncols, nnz;
+    const int64_t *colptr;
+    const int32_t *rowidx;
+    const double *val;
+};
+
+struct PruneArgs {
+    double theta;   // prune threshold
+    int S;          // select count (0 = off)
+    int R;          // recover count (0 = off)
+    double pct;     // recovery mass fraction
+    double r;       // inflation power
+};
+
+enum NumericMode { MODE_COUNT = 0, MODE_EXPAND = 1, MODE_ITERATE = 2 };
+
+// Per-column outputs of the numeric kernels.  Unused pointers may be null.
+struct NumericArgs {
+    DevCSC A, B;
+    const int32_t *cols;      // column ids handled by this launch
+    int32_t ncols;            // number of entries in cols
+    const int32_t *lo, *hi;   // row span bound of every product column
+    const int64_t *out_base;  // temp offset of every column (EXPAND / ITERATE)
+    const int64_t *capv;      // per-column key capacity (temp slot size); may be null
+    int32_t *out_row;
+    double *out_val;
+    int64_t *out_cnt;         // nnz written per column, -1 = table overflow
+    int64_t *nnz_prod;        // exact unpruned nnz per column (ITERATE)
+    double *delta;            // per-column max change (ITERATE)
+    int8_t *mode;             // per-column prune branch 0/1/2 (ITERATE)
+    PruneArgs pa;
+    const DevCSC *parts;      // merge mode: device array of nparts matrices (else null)
+    int32_t nparts;
+    const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
+};
+
+// ---- spgemm.hip
+constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
+int lds_bin_slots(int bin);                          // slots of bin
+int lds_bin_cap(int bin);                            // max distinct keys of bin
+void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
+                     const float *ckeys, int r, float *est, float *feat, const int64_t *prev_nnz,
+                     int iteration, hipStream_t st);
+void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float *keys, hipStream_t st);
+void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st);
+void launch_cohen_finish(const DevCSC &B, const float *colmin, int r, float *est, hipStream_t st);
+// Chooses the bin of every column (bins 0..6 LDS, 7 = HBM table) and its capacity.
+void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const int32_t *hi,
+                 const float *est, int est_kind, double est_scale, int64_t nrows,
+                 const uint8_t *col_active, int32_t *bin, int64_t *capv, int32_t *bin_count,
+                 int64_t *max_global, hipStream_t st);
+struct BinOffsets { int32_t off[8]; };
+void launch_scatter_bins(int64_t ncols, const int32_t *bin, const BinOffsets &bin_off, int32_t *cursor,
+                         int32_t *lists, hipStream_t st);
+void launch_scatter_bins_list(const int32_t *list, int32_t n, const int32_t *bin, const BinOffsets &off,
+                              int32_t *cursor, int32_t *out, hipStream_t st);
+void launch_bound_estimate(int64_t n, const int64_t *flops, const int32_t *lo, const int32_t *hi,
+                           int64_t nrows, float *est, hipStream_t st);
+void launch_replan(const int32_t *list, int32_t n, const int64_t *exact, int32_t *bin, int64_t *capv,
+                   int32_t *bin_count, int64_t *max_global, hipStream_t st);
+void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, const int32_t *lo,
+                       const int32_t *hi, int64_t nrows, int64_t *ub, int64_t *max_ub, hipStream_t st);
+void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,
+                      int region, hipStream_t st);
+void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
+                 int32_t *exact_list, int32_t *n_exact, hipStream_t st);
+void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
+                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
+                     hipStream_t st);
+constexpr int MAX_REGIONS = 8;
+struct TempRegions {
+    const int32_t *row[MAX_REGIONS];
+    const double *val[MAX_REGIONS];
+};
+void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st);
+int lds_bin_variants(int bin);
+void launch_numeric_global(NumericMode mode, const NumericArgs &a, int S, int cap, void *slab,
+                           size_t slab_bytes, int nslabs, hipStream_t st);
+size_t global_slab_bytes(int S, int cap);
+void launch_collect_overflow(int64_t ncols, const int32_t *cols, int32_t n, const int64_t *cnt,
+                             int32_t *ovf_list, int32_t *ovf_count, hipStream_t st);
+void launch_exscan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *block_tmp, hipStream_t st);
+int64_t exscan_tmp_elems(int64_t n);
+void launch_compact(int64_t ncols, const int32_t *bin, const int64_t *base, const int64_t *cnt,
+                    const int64_t *colptr, const TempRegions &tr, int32_t *row, double *val,
+                    hipStream_t st);
+void launch_copy_inactive(const DevCSC &A, const int32_t *col_comp, const uint8_t *active,
+                          const int64_t *colptr, int32_t *row, double *val, hipStream_t st);
+void launch_counts_inactive(const DevCSC &A, const int32_t *col_comp, const uint8_t *active,
+                            int64_t *cnt, double *delta, hipStream_t st);
+void launch_col_comp(int64_t ncols, const int64_t *comp_ptr, int64_t ncomp, int32_t *col_comp,
+                     const uint8_t *active, uint8_t *col_active, hipStream_t st);
+void launch_comp_max(int64_t ncomp, const int64_t *comp_ptr, const double *delta, double *out,
+                     hipStream_t st);
+void launch_validate(const DevCSC &A, int32_t *flag, hipStream_t st);
+void launch_reduce_stats(int64_t ncols, const int64_t *nnz_prod, const int8_t *mode,
+                         const double *delta, const int64_t *flops, int64_t *acc, double *dmax,
+                         hipStream_t st);
+
+// ---- prune.hip
+void launch_prune_plan(const DevCSC &B, const PruneArgs &pa, double *thr, int64_t *kept,
+                       int8_t *mode, hipStream_t st);
+void launch_prune_fill(const DevCSC &B, const double *thr, const int64_t *colptr, int32_t *row,
+                       double *val, hipStream_t st);
+void launch_inflate(int64_t ncols, const int64_t *colptr, double *val, double r, double *err,
+                    hipStream_t st);
+void launch_normalize(int64_t ncols, const int64_t *colptr, double *val, hipStream_t st);
+
+void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
+                       int32_t *hi, hipStream_t st);
+
+// ---- mlp.hip
+constexpr int MLP_IN = 12, MLP_H = 64;
+size_t mlp_packed_bytes();
+size_t mlp_state_floats();
+void launch_mlp_forward(const void *packed, const float *feat, int64_t rows, float *out,
+                        hipStream_t st);
+void launch_mlp_init(float *state, uint64_t seed, hipStream_t st);
+void launch_expm1_inplace(float *v, int64_t n, hipStream_t st);
+void launch_mlp_train_step(float *state, void *packed, const float *feat, const float *target,
+                           int64_t rows, float lr, float *loss_dev, float *grad_out,
+                           float *grad_tmp, hipStream_t st);
+size_t mlp_train_tmp_floats(int64_t rows);
+
+}  // namespace mcl

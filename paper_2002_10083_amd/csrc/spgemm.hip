@@ -1,0 +1,1425 @@
+// Expansion kernels for gfx950: symbolic pass, Cohen estimate, column binning,
+// per-bin hash-table SpGEMM with a fused prune / inflate / change epilogue,
+// an HBM-table variant for the heaviest columns, and compaction.
+//
+// Expansion (arXiv 2002.10083, Alg. 1): column j of B = A*A gathers
+// b_kj * A_*k for every nonzero b_kj of the column.  With CSC operands this is
+// column-wise Gustavson, which is what the paper's CSC-native formulation
+// computes (Section 3, "Sparse matrix storage format").  Work per column is
+// flops_j = sum_{k in B_*j} nnz(A_*k) (Section 2, "Notations").
+//
+// One workgroup (or one wavefront) owns one output column and a private hash
+// table of S slots (int32 row key + fp64 value) in LDS.  The nonzeros of B_*j
+// are visited in ascending k and, for each, all entries of A_*k are inserted
+// in parallel: rows inside one A_*k are distinct, so a k-step has no
+// conflicts, and k-steps are separated by a barrier.  Every output entry is
+// therefore accumulated as acc = fma(a_ik, b_kj, acc) in ascending k no
+// matter how the table is laid out -- results are bit-identical across table
+// sizes, bins and schedules.  The column is then sorted by row (bucket count
+// + in-bucket rank) and either written (expand) or pruned, inflated and
+// compared with the previous iterate in LDS (fused iteration).
+#include "device_common.hpp"
+#include "internal.hpp"
+
+#include <algorithm>
+
+namespace mcl {
+
+// ---------------------------------------------------------------------------
+// bins
+// ---------------------------------------------------------------------------
+// Temp-buffer offsets: base >= 0 is an offset in the main temp region;
+// base < 0 encodes -(1 + (region << 48 | offset)) for the fallback regions.
+constexpr int64_t REGION_MASK = ((int64_t)1 << 48) - 1;
+// Table slots per LDS bin and the maximum number of distinct keys it accepts
+// (load factor 3/4; more keys flag the column as overflowed).
+__host__ __device__ constexpr int bin_slots_c(int b) { return 128 << b; }
+__host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4; }
+int lds_bin_slots(int bin) { return bin_slots_c(bin); }
+int lds_bin_cap(int bin) { return bin_cap_c(bin); }
+
+// ---------------------------------------------------------------------------
+// symbolic pass: flops, row span, Cohen finish, MLP features
+// ---------------------------------------------------------------------------
+// One wavefront per column j of B.  For every nonzero b_kj: len = nnz(A_*k),
+// first and last row of A_*k.  Outputs flops_j, the row span [lo_j, hi_j] that
+// bounds the product column, and (optionally) Cohen's estimate from the
+// per-column key minima of A, and 12 MLP features.
+__global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *__restrict__ flops,
+                                                  int32_t *__restrict__ lo, int32_t *__restrict__ hi,
+                                                  const float *__restrict__ colmin, int r,
+                                                  float *__restrict__ est, float *__restrict__ feat,
+                                                  const int64_t *__restrict__ prev_nnz, int iteration)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (j >= B.ncols) return;
+    const int64_t bs = B.colptr[j], be = B.colptr[j + 1];
+    int64_t fl = 0, sq = 0, wlen = 0;
+    int mn = INT32_MAX, mx = -1, lmax = 0, lmin = INT32_MAX;
+    double bmax = 0.0, bsq = 0.0, wl = 0.0;
+    float cm[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) cm[l] = INFINITY;
+    for (int64_t p = bs + lane(); p < be; p += WAVE) {
+        const int k = B.rowidx[p];
+        const double b = B.val[p];
+        const int64_t a0 = A.colptr[k], a1 = A.colptr[k + 1];
+        const int len = (int)(a1 - a0);
+        fl += len;
+        sq += (int64_t)len * len;
+        lmax = max(lmax, len);
+        lmin = min(lmin, len);
+        bmax = fmax(bmax, b);
+        bsq += b * b;
+        wl += b * (double)len;
+        if (len > 0) {
+            mn = min(mn, A.rowidx[a0]);
+            mx = max(mx, A.rowidx[a1 - 1]);
+        }
+        if (colmin) {
+#pragma unroll
+            for (int l = 0; l < 16; ++l)
+                if (l < r) cm[l] = fminf(cm[l], colmin[(int64_t)k * r + l]);
+        }
+    }
+    fl = wave_sum_i64(fl);
+    sq = wave_sum_i64(sq);
+    mn = wave_min_i(mn);
+    mx = wave_max_i(mx);
+    lmax = wave_max_i(lmax);
+    lmin = wave_min_i(lmin);
+    bmax = wave_max(bmax);
+    bsq = wave_sum(bsq);
+    wl = wave_sum(wl);
+    float esum = 0.f;
+    bool reached = true;
+    if (colmin) {
+#pragma unroll
+        for (int l = 0; l < 16; ++l) {
+            if (l < r) {
+                float v = cm[l];
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, WAVE));
+                if (!(v < INFINITY)) reached = false;
+                esum += v;
+            }
+        }
+    }
+    (void)wlen;
+    if (lane() == 0) {
+        flops[j] = fl;
+        lo[j] = (mx >= 0) ? mn : 0;
+        hi[j] = (mx >= 0) ? mx : 0;
+        if (colmin && est) est[j] = (reached && fl > 0) ? (float)(r - 1) / esum : 0.f;
+        if (feat) {
+            const int m = (int)(be - bs);
+            const double mean = m ? (double)fl / m : 0.0;
+            const double var = m ? fmax((double)sq / m - mean * mean, 0.0) : 0.0;
+            float *f = feat + j * 12;
+            f[0] = log1pf((float)m);
+            f[1] = log1pf((float)fl);
+            f[2] = log1pf((float)lmax);
+            f[3] = log1pf((float)mean);
+            f[4] = log1pf((float)(m ? lmin : 0));
+            f[5] = (float)iteration;
+            f[6] = log1pf((float)((mx >= 0) ? (mx - mn + 1) : 0));
+            f[7] = (float)bmax;
+            f[8] = (float)bsq;
+            f[9] = log1pf((float)sqrt(var));
+            f[10] = prev_nnz ? log1pf((float)prev_nnz[j]) : 0.f;
+            f[11] = log1pf((float)wl);
+        }
+    }
+}
+
+void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
+                     const float *colmin, int r, float *est, float *feat, const int64_t *prev_nnz,
+                     int iteration, hipStream_t st)
+{
+    if (B.ncols == 0) return;
+    const unsigned grid = (unsigned)((B.ncols + 3) / 4);
+    hipLaunchKernelGGL(k_symbolic, dim3(grid), dim3(256), 0, st, A, B, flops, lo, hi, colmin, r, est,
+                       feat, prev_nnz, iteration);
+}
+
+// Merge planning: for column j, ub_j = sum over parts of nnz (the exact-safe
+// bound on the merged column) and the row span over all parts.
+__global__ __launch_bounds__(256) void k_merge_plan(const DevCSC *__restrict__ parts, int nparts,
+                                                    int64_t ncols, int64_t *__restrict__ ub,
+                                                    int32_t *__restrict__ lo, int32_t *__restrict__ hi)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = 0;
+        int mn = INT32_MAX, mx = -1;
+        for (int l = 0; l < nparts; ++l) {
+            const DevCSC &P = parts[l];
+            const int64_t s = P.colptr[j], e = P.colptr[j + 1];
+            n += e - s;
+            if (e > s) {
+                mn = min(mn, P.rowidx[s]);
+                mx = max(mx, P.rowidx[e - 1]);
+            }
+        }
+        ub[j] = n;
+        lo[j] = (mx >= 0) ? mn : 0;
+        hi[j] = (mx >= 0) ? mx : 0;
+    }
+}
+
+void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
+                       int32_t *hi, hipStream_t st)
+{
+    if (ncols == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_merge_plan, dim3(grid), dim3(256), 0, st, parts, nparts, ncols, ub, lo, hi);
+}
+
+// ---------------------------------------------------------------------------
+// Cohen's estimator (Section 6): exponential keys on the first layer (rows of
+// A), minimum over each column of A, then over each column of B.
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output t of the generator
+// seeded with s is mix(s + (t+1) * gamma).  The stream of MCL iteration `it`
+// is seeded with output `it` of SplitMix64(seed); key (i, l) uses output
+// i*r + l of that stream, mapped to U in (0, 1], key = -ln U.
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t sm64_out(uint64_t seed, uint64_t t)
+{
+    return sm64_mix(seed + (t + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+__global__ __launch_bounds__(256) void k_cohen_keys(int64_t nrows, int r, uint64_t seed, int it,
+                                                    float *__restrict__ keys)
+{
+    const uint64_t s = sm64_out(seed, (uint64_t)it);
+    const int64_t n = nrows * r;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = sm64_out(s, (uint64_t)q);
+        const double u = (double)((x >> 11) + 1ull) * (1.0 / 9007199254740992.0);
+        keys[q] = (float)(-log(u));
+    }
+}
+
+void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float *keys,
+                       hipStream_t st)
+{
+    if (nrows == 0) return;
+    hipLaunchKernelGGL(k_cohen_keys, dim3(2048), dim3(256), 0, st, nrows, r, seed, iteration, keys);
+}
+
+// colmin[k*r + l] = min over rows i of A_*k of key(i, l).  One wave per column.
+__global__ __launch_bounds__(256) void k_cohen_colmin(DevCSC A, const float *__restrict__ keys, int r,
+                                                      float *__restrict__ colmin)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (k >= A.ncols) return;
+    float cm[16];
+#pragma unroll
+    for (int l = 0; l < 16; ++l) cm[l] = INFINITY;
+    for (int64_t p = A.colptr[k] + lane(); p < A.colptr[k + 1]; p += WAVE) {
+        const int64_t i = A.rowidx[p];
+#pragma unroll
+        for (int l = 0; l < 16; ++l)
+            if (l < r) cm[l] = fminf(cm[l], keys[i * r + l]);
+    }
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+        if (l < r) {
+            float v = cm[l];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, WAVE));
+            if (lane() == 0) colmin[k * r + l] = v;
+        }
+    }
+}
+
+void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st)
+{
+    if (A.ncols == 0) return;
+    hipLaunchKernelGGL(k_cohen_colmin, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A, keys,
+                       r, colmin);
+}
+
+void launch_cohen_finish(const DevCSC &, const float *, int, float *, hipStream_t) {}
+
+// ---------------------------------------------------------------------------
+// planning: per column table size and bin
+// ---------------------------------------------------------------------------
+// need_j = the number of distinct keys the table must accept.  Columns whose
+// exact-safe bound ub_j = min(flops_j, row span_j, nrows) fits the 1024-slot
+// bin use the bound (no estimate, no overflow possible).  Larger columns use
+// the estimate scaled by 1.3 * est_scale (clamped to ub_j).  The bin is the
+// smallest LDS table whose capacity holds need_j; beyond 8192 slots the
+// column goes to the HBM-table kernel (bin 7) sized by need_j.
+__global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__restrict__ flops,
+                                              const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
+                                              const float *__restrict__ est, int est_kind,
+                                              double est_scale, int64_t nrows,
+                                              const uint8_t *__restrict__ col_active,
+                                              int32_t *__restrict__ bin, int64_t *__restrict__ capv,
+                                              int32_t *__restrict__ bin_count,
+                                              unsigned long long *__restrict__ max_global)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        if (col_active && !col_active[j]) { bin[j] = -1; capv[j] = 0; continue; }
+        const int64_t fl = flops[j];
+        int64_t ub = fl;
+        if (fl > 0) ub = min(ub, (int64_t)(hi[j] - lo[j] + 1));
+        ub = min(ub, nrows);
+        int64_t need = ub;
+        bool try_lds = false;
+        if (est_kind != 0 && est && ub > bin_cap_c(3)) {
+            double e = ceil(1.3 * est_scale * (double)est[j]);
+            if (e < 1.0) e = 1.0;
+            need = min(ub, (int64_t)e);
+            // an estimate near the largest LDS table still tries LDS first
+            try_lds = (double)est[j] <= 1.25 * bin_cap_c(NUM_LDS_BINS - 1);
+        }
+        int b = 0;
+        while (b < NUM_LDS_BINS && bin_cap_c(b) < need) ++b;
+        if (b == NUM_LDS_BINS && try_lds) b = NUM_LDS_BINS - 1;
+        bin[j] = b;
+        capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
+        atomicAdd(&bin_count[b], 1);
+        if (b == NUM_LDS_BINS) atomicMax(max_global, (unsigned long long)need);
+    }
+}
+
+void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const int32_t *hi,
+                 const float *est, int est_kind, double est_scale, int64_t nrows,
+                 const uint8_t *col_active, int32_t *bin, int64_t *capv, int32_t *bin_count,
+                 int64_t *max_global, hipStream_t st)
+{
+    if (ncols == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, st, ncols, flops, lo, hi, est, est_kind,
+                       est_scale, nrows, col_active, bin, capv, bin_count,
+                       (unsigned long long *)max_global);
+}
+
+// Scatter the listed columns into per-bin lists by bin[j].
+__global__ __launch_bounds__(256) void k_scatter_bins_list(const int32_t *__restrict__ list, int32_t n,
+                                                           const int32_t *__restrict__ bin,
+                                                           BinOffsets bin_off, int32_t *__restrict__ cursor,
+                                                           int32_t *__restrict__ out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int j = list[i];
+        const int b = bin[j];
+        out[bin_off.off[b] + atomicAdd(&cursor[b], 1)] = j;
+    }
+}
+
+void launch_scatter_bins_list(const int32_t *list, int32_t n, const int32_t *bin, const BinOffsets &off,
+                              int32_t *cursor, int32_t *out, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scatter_bins_list, dim3(grid), dim3(256), 0, st, list, n, bin, off, cursor, out);
+}
+
+// est_j = min(flops_j, row span_j, nrows): the exact-safe bound as an estimate.
+__global__ void k_bound_estimate(int64_t n, const int64_t *__restrict__ flops, const int32_t *__restrict__ lo,
+                                 const int32_t *__restrict__ hi, int64_t nrows, float *__restrict__ est)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t u = flops[j];
+        if (u > 0) u = min(u, (int64_t)(hi[j] - lo[j] + 1));
+        est[j] = (float)min(u, nrows);
+    }
+}
+
+void launch_bound_estimate(int64_t n, const int64_t *flops, const int32_t *lo, const int32_t *hi,
+                           int64_t nrows, float *est, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_bound_estimate, dim3(grid), dim3(256), 0, st, n, flops, lo, hi, nrows, est);
+}
+
+// Re-plan of overflowed columns from their exact product size m_j: the
+// smallest LDS bin that holds m_j, else the HBM table sized for m_j.
+__global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list, int32_t n,
+                                                const int64_t *__restrict__ exact,
+                                                int32_t *__restrict__ bin, int64_t *__restrict__ capv,
+                                                int32_t *__restrict__ bin_count,
+                                                unsigned long long *__restrict__ max_global)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int j = list[i];
+        const int64_t need = exact[j];
+        int b = 0;
+        while (b < NUM_LDS_BINS && bin_cap_c(b) < need) ++b;
+        bin[j] = b;
+        capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
+        atomicAdd(&bin_count[b], 1);
+        if (b == NUM_LDS_BINS) atomicMax(max_global, (unsigned long long)need);
+    }
+}
+
+void launch_replan(const int32_t *list, int32_t n, const int64_t *exact, int32_t *bin, int64_t *capv,
+                   int32_t *bin_count, int64_t *max_global, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_replan, dim3(grid), dim3(256), 0, st, list, n, exact, bin, capv, bin_count,
+                       (unsigned long long *)max_global);
+}
+
+// Exact-safe bound ub_j = min(flops_j, row span_j, nrows) of the listed
+// columns, written to ub[j]; the maximum goes to *max_ub.
+__global__ __launch_bounds__(256) void k_list_bound(const int32_t *__restrict__ list, int32_t n,
+                                                    const int64_t *__restrict__ flops,
+                                                    const int32_t *__restrict__ lo,
+                                                    const int32_t *__restrict__ hi, int64_t nrows,
+                                                    int64_t *__restrict__ ub,
+                                                    unsigned long long *__restrict__ max_ub)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int j = list[i];
+        int64_t u = flops[j];
+        if (u > 0) u = min(u, (int64_t)(hi[j] - lo[j] + 1));
+        u = min(u, nrows);
+        ub[j] = u;
+        atomicMax(max_ub, (unsigned long long)u);
+    }
+}
+
+void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, const int32_t *lo,
+                       const int32_t *hi, int64_t nrows, int64_t *ub, int64_t *max_ub, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_list_bound, dim3(grid), dim3(256), 0, st, list, n, flops, lo, hi, nrows, ub,
+                       (unsigned long long *)max_ub);
+}
+
+// Temp offsets of the listed columns after the main region: base[j] =
+// -(1 + offset) into the second temp buffer (prefix of capv over the list).
+__global__ void k_list_base(const int32_t *__restrict__ list, int32_t n, const int64_t *__restrict__ capv,
+                            int64_t *__restrict__ base, int64_t *__restrict__ total, int region)
+{
+    // single wave, sequential chunks of 64 (the list is short)
+    int64_t run = 0;
+    for (int c = 0; c < n; c += WAVE) {
+        const int i = c + lane();
+        const int64_t v = (i < n) ? capv[list[i]] : 0;
+        int64_t x = v;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, WAVE);
+            if (lane() >= d) x += y;
+        }
+        if (i < n) base[list[i]] = -(1 + (((int64_t)region << 48) | (run + x - v)));
+        run += __shfl(x, WAVE - 1, WAVE);
+    }
+    if (lane() == 0) *total = run;
+}
+
+void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,
+                      int region, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_list_base, dim3(1), dim3(WAVE), 0, st, list, n, capv, base, total, region);
+}
+
+// Overflowed columns move one LDS bin up (twice the table); columns that
+// overflowed the largest LDS bin are flagged for an exact count (bin 7).
+__global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, int32_t n,
+                                              int32_t *__restrict__ bin, int64_t *__restrict__ capv,
+                                              int32_t *__restrict__ bin_count,
+                                              int32_t *__restrict__ exact_list,
+                                              int32_t *__restrict__ n_exact)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int j = list[i];
+        const int b = bin[j];
+        if (b + 1 < NUM_LDS_BINS) {
+            bin[j] = b + 1;
+            capv[j] = bin_cap_c(b + 1);
+            atomicAdd(&bin_count[b + 1], 1);
+        } else {
+            exact_list[atomicAdd(n_exact, 1)] = j;
+        }
+    }
+}
+
+void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
+                 int32_t *exact_list, int32_t *n_exact, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_bump, dim3(grid), dim3(256), 0, st, list, n, bin, capv, bin_count, exact_list,
+                       n_exact);
+}
+
+// Per-bin totals of the launched columns: flops, nnz(B_*j), output count.
+__global__ __launch_bounds__(256) void k_bin_sums(const int32_t *__restrict__ lists, BinOffsets off,
+                                                  BinOffsets cnt, const int64_t *__restrict__ flops,
+                                                  const int64_t *__restrict__ bcolptr,
+                                                  const int64_t *__restrict__ out_cnt,
+                                                  unsigned long long *__restrict__ acc)
+{
+    const int b = blockIdx.y;
+    int64_t f = 0, bn = 0, o = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt.off[b]; i += gridDim.x * blockDim.x) {
+        const int j = lists[off.off[b] + i];
+        f += flops[j];
+        if (bcolptr) bn += bcolptr[j + 1] - bcolptr[j];
+        o += max(out_cnt[j], (int64_t)0);
+    }
+    f = wave_sum_i64(f);
+    bn = wave_sum_i64(bn);
+    o = wave_sum_i64(o);
+    if (lane() == 0) {
+        atomicAdd(&acc[3 * b + 0], (unsigned long long)f);
+        atomicAdd(&acc[3 * b + 1], (unsigned long long)bn);
+        atomicAdd(&acc[3 * b + 2], (unsigned long long)o);
+    }
+}
+
+void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
+                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bin_sums, dim3(64, 8), dim3(256), 0, st, lists, off, cnt, flops, bcolptr, out_cnt,
+                       (unsigned long long *)acc);
+}
+
+__global__ __launch_bounds__(256) void k_scatter_bins(int64_t ncols, const int32_t *__restrict__ bin,
+                                                      BinOffsets bin_off, int32_t *__restrict__ cursor,
+                                                      int32_t *__restrict__ lists)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int b = bin[j];
+        if (b < 0) continue;
+        const int pos = atomicAdd(&cursor[b], 1);
+        lists[bin_off.off[b] + pos] = (int32_t)j;
+    }
+}
+
+void launch_scatter_bins(int64_t ncols, const int32_t *bin, const BinOffsets &bin_off, int32_t *cursor,
+                         int32_t *lists, hipStream_t st)
+{
+    if (ncols == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_scatter_bins, dim3(grid), dim3(256), 0, st, ncols, bin, bin_off, cursor,
+                       lists);
+}
+
+// ---------------------------------------------------------------------------
+// numeric column kernel (shared by the LDS bins and the HBM-table variant)
+// ---------------------------------------------------------------------------
+template <typename IdxT>
+struct Scratch {
+    int32_t *key;    // S slots
+    double *val;     // S slots
+    IdxT *list;      // cap: bucketed slots, later the kept list
+    IdxT *sorted;    // cap: slots in ascending row order
+    int *bcnt;       // NB bucket offsets
+    int *bcur;       // NB bucket cursors
+    double *p0, *p1; // per 64-block partial sums (cap/64 + 1)
+    int *ip;         // per 64-block counts
+    int *hist;       // 256-bin histogram
+    int *misc;       // 16 ints: [0] nkeys [1] overflow [2..] broadcast
+    double *dmisc;   // 4 doubles
+    int *wsum;       // NT/64 ints for scans
+};
+
+// Find row `key` in the open-addressing table or insert it.  A new key first
+// reserves one unit of the capacity counter, so the table never holds more
+// than `cap` < S keys and probing always terminates.  Returns the slot, or -1
+// (and raises the overflow flag) when the capacity is exhausted.
+__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logS, int mask, int *nkeys,
+                                              int cap, int *ovf)
+{
+    uint32_t h = hash_slot(k, logS);
+    for (;;) {
+        const int cur = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == k) return (int)h;
+        if (cur == EMPTY_KEY) {
+            const int r = atomicAdd(nkeys, 1);
+            if (r >= cap) {
+                atomicSub(nkeys, 1);
+                *ovf = 1;
+                return -1;
+            }
+            const int old = atomicCAS(&key[h], EMPTY_KEY, k);
+            if (old == EMPTY_KEY) return (int)h;
+            atomicSub(nkeys, 1);
+            if (old == k) return (int)h;
+        }
+        h = (h + 1) & (uint32_t)mask;
+    }
+}
+
+__device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logS, int mask)
+{
+    uint32_t h = hash_slot(k, logS);
+    for (;;) {
+        const int cur = key[h];
+        if (cur == k) return (int)h;
+        if (cur == EMPTY_KEY) return -1;
+        h = (h + 1) & (uint32_t)mask;
+    }
+}
+
+__device__ __forceinline__ int bucket_of(int32_t k, int32_t lo, uint64_t mul, int NB)
+{
+    const int b = (int)(((uint64_t)(uint32_t)(k - lo) * mul) >> 32);
+    return min(max(b, 0), NB - 1);
+}
+
+// Exact k-th largest (kth >= 1) of m positive doubles get(p), p < m, by an
+// MSD radix select over their IEEE bit patterns (monotone for positive
+// values), 8 bits per pass.  Called by all NT threads of the group.
+template <int NT, bool GS, typename Get>
+__device__ double radix_kth_largest(Get get, int m, int kth, int *hist, int *misc)
+{
+    const int tid = threadIdx.x % NT;
+    const bool w0 = tid < WAVE;
+    uint64_t prefix = 0, pmask = 0;
+    int kk = kth;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += NT) hist[i] = 0;
+        group_sync<NT, GS>();
+        for (int p = tid; p < m; p += NT) {
+            const uint64_t u = (uint64_t)__double_as_longlong(get(p));
+            if ((u & pmask) == prefix) atomicAdd(&hist[(u >> shift) & 255], 1);
+        }
+        group_sync<NT, GS>();
+        if (w0) {
+            // lane l owns digits 4l..4l+3; find digit d with
+            // count(digits > d) < kk <= count(digits >= d)
+            const int l = lane();
+            const int c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+            int x = c0 + c1 + c2 + c3;
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const int y = __shfl_down(x, d, WAVE);
+                if (l + d < WAVE) x += y;
+            }
+            int above = __shfl_down(x, 1, WAVE);
+            if (l == WAVE - 1) above = 0;
+            if (above < kk && kk <= x) {
+                int dsel = 4 * l, knew = kk;
+                const int cs[4] = {c3, c2, c1, c0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (above + cs[q] >= kk) { dsel = 4 * l + 3 - q; knew = kk - above; break; }
+                    above += cs[q];
+                }
+                misc[4] = dsel;
+                misc[5] = knew;
+            }
+        }
+        group_sync<NT, GS>();
+        const int d = misc[4];
+        kk = misc[5];
+        prefix |= (uint64_t)d << shift;
+        pmask |= 255ull << shift;
+        group_sync<NT, GS>();
+    }
+    return __longlong_as_double((long long)prefix);
+}
+
+// Prune decision shared by the fused kernel and the stand-alone prune: the
+// fixed-tree sums of the column (mB) and of its entries >= theta (mP), the
+// count nP, and the resulting branch and threshold (recover / select /
+// threshold).  get(p) returns the value at sorted position p < m.
+template <int NT, bool GS, typename Get>
+__device__ void prune_decide(Get get, int m, const PruneArgs &pa, double *p0, double *p1, int *ip,
+                             int *hist, int *misc, double *dmisc, int *out_mode, double *out_t)
+{
+    const int tid = threadIdx.x % NT;
+    const int w = tid / WAVE;
+    constexpr int NWV = (NT + WAVE - 1) / WAVE;
+    const int nblk = (m + WAVE - 1) / WAVE;
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const double v = (p < m) ? get(p) : 0.0;
+        const bool ab = (p < m) && (v >= pa.theta);
+        const double sB = wave_sum(v);
+        const double sP = wave_sum(ab ? v : 0.0);
+        const int c = __popcll(ballot(ab));
+        if (lane() == 0) { p0[b] = sB; p1[b] = sP; ip[b] = c; }
+    }
+    group_sync<NT, GS>();
+    if (tid < WAVE) {
+        const double mB = fixed_tree_finish(p0, nblk);
+        const double mP = fixed_tree_finish(p1, nblk);
+        int nP = 0;
+        for (int b = lane(); b < nblk; b += WAVE) nP += ip[b];
+        nP = wave_sum_i(nP);
+        int mode = 0, kth = 0;
+        double t = pa.theta;
+        const bool rec = pa.R > 0 && nP < pa.R && mP < pa.pct * mB;
+        const bool sel = !rec && pa.S > 0 && nP > pa.S;
+        if (rec) {
+            mode = 1;
+            if (m >= pa.R) kth = pa.R; else t = 0.0;
+        } else if (sel) {
+            mode = 2;
+            kth = pa.S;
+        }
+        if (lane() == 0) { misc[2] = mode; misc[3] = kth; dmisc[0] = t; }
+    }
+    group_sync<NT, GS>();
+    const int mode = misc[2], kth = misc[3];
+    double t = dmisc[0];
+    group_sync<NT, GS>();
+    if (kth > 0) t = radix_kth_largest<NT, GS>(get, m, kth, hist, misc);
+    *out_mode = mode;
+    *out_t = t;
+}
+
+// The numeric body for one column j, executed by NT threads.
+template <int NT, int MODE, int E, int D, typename IdxT, bool IS_MERGE, bool GS>
+__device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, int cap, int NB,
+                           const Scratch<IdxT> &sc)
+{
+    const int tid = threadIdx.x % NT;
+    const int w = tid / WAVE;
+    constexpr int NWV = (NT + WAVE - 1) / WAVE;
+    const int mask = S - 1;
+    if (a.capv) cap = (int)min((int64_t)cap, a.capv[j]);
+    int32_t *tkey = sc.key;
+    double *tval = sc.val;
+
+    for (int s = tid; s < S; s += NT) {
+        tkey[s] = EMPTY_KEY;
+        if (MODE != MODE_COUNT) tval[s] = 0.0;
+    }
+    if (tid == 0) { sc.misc[0] = 0; sc.misc[1] = 0; }
+    group_sync<NT, GS>();
+
+    // ---------------- accumulation ----------------
+    // Step t of column j adds b_t * (column t of the source) to the table:
+    // SpGEMM: source column = A_*k for the t-th nonzero b_kj of B_*j;
+    // merge:  source column = column j of part t, with b_t = 1 (fma(v, 1, acc)
+    //         is the correctly rounded acc + v, so parts are summed in order).
+    const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
+    const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
+    bool overflow = false;
+    for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
+        // lane l of every wave holds step tb + l: row/value pointers, length, b
+        const int t = tb + lane();
+        const int32_t *rp = nullptr;
+        const double *vp = nullptr;
+        int klen = 0;
+        double bv = 1.0;
+        if (t < mj) {
+            if constexpr (IS_MERGE) {
+                const DevCSC &P = a.parts[t];
+                const int64_t p0 = P.colptr[j];
+                rp = P.rowidx + p0;
+                vp = P.val + p0;
+                klen = (int)(P.colptr[j + 1] - p0);
+            } else {
+                const int k = a.B.rowidx[bs + t];
+                bv = a.B.val[bs + t];
+                const int64_t p0 = a.A.colptr[k];
+                rp = a.A.rowidx + p0;
+                vp = a.A.val + p0;
+                klen = (int)(a.A.colptr[k + 1] - p0);
+            }
+        }
+        const int nb = min(WAVE, mj - tb);
+        // Every step of the batch is cut into ceil(len/CH) chunks (at least
+        // one, possibly empty); the total is known up front so the ring below
+        // runs a fixed number of rounds with no early exit.
+        constexpr int CH = NT * E;
+        const int nchunk_l = (lane() < nb) ? max(1, (klen + CH - 1) / CH) : 0;
+        const int total = wave_sum_i(nchunk_l);
+        // Ring of D chunks in flight: chunk c+D is requested right after
+        // chunk c has been folded into the table, so D-1 chunks of loads
+        // overlap every table update.  Chunks are consumed in load order,
+        // which keeps the ascending-k accumulation order.  Every load is
+        // issued unconditionally (lanes past the end read a valid dummy
+        // word and carry a cleared validity bit) and the iterator advances
+        // with selects, so the compiler can keep the loads outstanding.
+        const int32_t *dummy_r = (const int32_t *)a.dummy;
+        const double *dummy_v = (const double *)a.dummy;
+        int iu = 0, ioff = 0;
+        int32_t rr[D][E];
+        double vv[D][E];
+        bool vb[D][E];
+        double bb[D];
+        auto issue = [&](int32_t(&r)[E], double(&v)[E], bool(&in)[E], double &b) {
+            const int ul = min(iu, WAVE - 1);
+            const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, ul);
+            const double *vbp = (const double *)readlane_i64((int64_t)vp, ul);
+            const int len0 = readlane_i(klen, ul);
+            const int len = (iu < nb) ? len0 : 0;
+            b = readlane_d(bv, ul);
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int e = ioff + tid + q * NT;
+                in[q] = e < len;
+                r[q] = ldg(in[q] ? rb + e : dummy_r);
+                if (MODE != MODE_COUNT) v[q] = ldg(in[q] ? vbp + e : dummy_v);
+            }
+            const bool more = ioff + CH < len;
+            ioff = more ? ioff + CH : 0;
+            iu = more ? iu : iu + 1;
+        };
+#pragma unroll
+        for (int i = 0; i < D; ++i) issue(rr[i], vv[i], vb[i], bb[i]);
+        const int rounds = (total + D - 1) / D;
+        for (int rd = 0; rd < rounds; ++rd) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    if (vb[i][q] && !overflow) {
+                        const int s = find_or_insert(tkey, rr[i][q], logS, mask, &sc.misc[0], cap,
+                                                     &sc.misc[1]);
+                        if (MODE != MODE_COUNT && s >= 0) tval[s] = fma(vv[i][q], bb[i], tval[s]);
+                    }
+                }
+                group_sync<NT, GS>();
+                overflow = sc.misc[1] != 0;
+                issue(rr[i], vv[i], vb[i], bb[i]);
+            }
+        }
+    }
+    group_sync<NT, GS>();
+    const int m = sc.misc[0];
+    if (sc.misc[1]) {
+        if (tid == 0) a.out_cnt[j] = -1;
+        return;
+    }
+    if (MODE == MODE_COUNT) {
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+
+    // ---------------- sort the m keys by row ----------------
+    const int32_t lo = a.lo[j];
+    const int64_t span = (int64_t)a.hi[j] - lo + 1;
+    const uint64_t mul = (span <= NB) ? (1ull << 32) : (((uint64_t)NB << 32) / (uint64_t)span);
+    for (int b = tid; b < NB; b += NT) sc.bcnt[b] = 0;
+    group_sync<NT, GS>();
+    for (int s = tid; s < S; s += NT) {
+        const int k = tkey[s];
+        if (k != EMPTY_KEY) atomicAdd(&sc.bcnt[bucket_of(k, lo, mul, NB)], 1);
+    }
+    group_sync<NT, GS>();
+    block_exscan<NT, GS>(sc.bcnt, NB, sc.wsum);
+    for (int b = tid; b < NB; b += NT) sc.bcur[b] = sc.bcnt[b];
+    group_sync<NT, GS>();
+    for (int s = tid; s < S; s += NT) {
+        const int k = tkey[s];
+        if (k != EMPTY_KEY) {
+            const int pos = atomicAdd(&sc.bcur[bucket_of(k, lo, mul, NB)], 1);
+            sc.list[pos] = (IdxT)s;
+        }
+    }
+    group_sync<NT, GS>();
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    for (int p = tid; p < m; p += NT) {
+        const int s = sc.list[p];
+        const int k = tkey[s];
+        const int b = bucket_of(k, lo, mul, NB);
+        const int st = sc.bcnt[b];
+        const int en = (b + 1 < NB) ? sc.bcnt[b + 1] : m;
+        int rank = st;
+        for (int q = st; q < en; ++q) rank += (tkey[sc.list[q]] < k) ? 1 : 0;
+        if (MODE == MODE_EXPAND) {
+            a.out_row[base + rank] = k;
+            a.out_val[base + rank] = tval[s];
+        } else {
+            sc.sorted[rank] = (IdxT)s;
+        }
+    }
+    if (MODE == MODE_EXPAND) {
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+    group_sync<NT, GS>();
+
+    // ---------------- prune (Alg. 1) ----------------
+    auto getv = [&](int p) { return tval[sc.sorted[p]]; };
+    int pmode;
+    double t;
+    prune_decide<NT, GS>(getv, m, a.pa, sc.p0, sc.p1, sc.ip, sc.hist, sc.misc, sc.dmisc, &pmode, &t);
+
+    // kept entries, in row order, into sc.list
+    const int nblk = (m + WAVE - 1) / WAVE;
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const bool keep = (p < m) && (getv(p) >= t);
+        const int c = __popcll(ballot(keep));
+        if (lane() == 0) sc.ip[b] = c;
+    }
+    group_sync<NT, GS>();
+    const int K = block_exscan<NT, GS>(sc.ip, nblk, sc.wsum);
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const bool keep = (p < m) && (getv(p) >= t);
+        const uint64_t mk = ballot(keep);
+        if (keep) sc.list[sc.ip[b] + popc_below(mk)] = sc.sorted[p];
+    }
+    group_sync<NT, GS>();
+
+    // ---------------- inflation: c^r / column sum (fixed tree over kept rank) ----------------
+    const double r = a.pa.r;
+    const int kblk = (K + WAVE - 1) / WAVE;
+    for (int b = w; b < kblk; b += NWV) {
+        const int q = b * WAVE + lane();
+        const double c = (q < K) ? inflate_pow(tval[sc.list[q]], r) : 0.0;
+        const double bsum = wave_sum(c);
+        if (lane() == 0) sc.p0[b] = bsum;
+    }
+    group_sync<NT, GS>();
+    if (tid < WAVE) {
+        const double ssum = fixed_tree_finish(sc.p0, kblk);
+        if (lane() == 0) sc.dmisc[1] = ssum;
+    }
+    // dropped entries read as 0 in the change computation
+    for (int p = tid; p < m; p += NT) {
+        const int s = sc.sorted[p];
+        if (tval[s] < t) tval[s] = 0.0;
+    }
+    group_sync<NT, GS>();
+    const double ssum = sc.dmisc[1];
+    for (int q = tid; q < K; q += NT) {
+        const int s = sc.list[q];
+        const double c = inflate_pow(tval[s], r);
+        const double an = (ssum > 0.0) ? c / ssum : 0.0;
+        a.out_row[base + q] = tkey[s];
+        a.out_val[base + q] = an;
+        tval[s] = an;
+    }
+    group_sync<NT, GS>();
+
+    // ---------------- change vs the previous iterate (A_*j == B_*j) ----------------
+    double dmax = 0.0;
+    for (int t2 = tid; t2 < mj; t2 += NT) {
+        const int k = a.B.rowidx[bs + t2];
+        const double old = a.B.val[bs + t2];
+        const int s = find_slot(tkey, k, logS, mask);
+        if (s >= 0) {
+            dmax = fmax(dmax, fabs(tval[s] - old));
+            tval[s] = -1.0;  // matched
+        } else {
+            dmax = fmax(dmax, old);
+        }
+    }
+    group_sync<NT, GS>();
+    for (int q = tid; q < K; q += NT) dmax = fmax(dmax, tval[sc.list[q]]);  // unmatched new entries
+    dmax = wave_max(dmax);
+    if constexpr (NT > WAVE) {
+        if (lane() == 0) sc.p1[w] = dmax;
+        group_sync<NT, GS>();
+        if (tid == 0) {
+            for (int q = 1; q < NWV; ++q) dmax = fmax(dmax, sc.p1[q]);
+        }
+    }
+    if (tid == 0) {
+        a.out_cnt[j] = K;
+        if (a.nnz_prod) a.nnz_prod[j] = m;
+        if (a.delta) a.delta[j] = dmax;
+        if (a.mode) a.mode[j] = (int8_t)pmode;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-bin kernels
+// ---------------------------------------------------------------------------
+template <int S>
+struct LdsBin {
+    static constexpr int CAP = (3 * S) / 4;
+    static constexpr int NB = (S / 4 < 64) ? 64 : S / 4;
+    static constexpr int NBLK = CAP / WAVE + 2;
+    using Idx = uint16_t;
+};
+
+template <int S, int NW, int CPW, int MODE, int E, int D, bool IS_MERGE>
+__global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
+{
+    using L = LdsBin<S>;
+    constexpr int NT = NW * WAVE;
+    struct Col {
+        double val[S];
+        int32_t key[S];
+        double p0[L::NBLK], p1[L::NBLK];
+        int32_t bcnt[L::NB], bcur[L::NB];
+        int32_t ip[L::NBLK];
+        int32_t hist[256];
+        uint16_t list[L::CAP], sorted[L::CAP];
+        int32_t misc[16];
+        double dmisc[4];
+        int32_t wsum[NW];
+    };
+    __shared__ Col cols[CPW];
+    const int ci = threadIdx.x / NT;
+    const int64_t idx = (int64_t)blockIdx.x * CPW + ci;
+    if (idx >= a.ncols) return;  // whole groups exit together
+    Col &c = cols[ci];
+    Scratch<uint16_t> sc{c.key, c.val, c.list, c.sorted, c.bcnt, c.bcur, c.p0, c.p1,
+                         c.ip, c.hist, c.misc, c.dmisc, c.wsum};
+    constexpr int logS = __builtin_ctz(S);
+    column_body<NT, MODE, E, D, uint16_t, IS_MERGE, false>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
+}
+
+// Launch shapes per bin: (waves per column, columns per workgroup, entries
+// per lane per chunk, chunks in flight).  Variant 0 is the default; the
+// others are alternatives the tuner may select through mcl_params.bin_policy
+// (4 bits per bin).  Merge and exact-count launches always use variant 0.
+template <int MODE, bool IS_MERGE>
+static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStream_t st)
+{
+    const int n = a.ncols;
+    if (n <= 0) return;
+#define MCL_LAUNCH(S_, NW_, CPW_, E_, D_)                                                   \
+    hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE>),              \
+                       dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
+    if (IS_MERGE || MODE == MODE_COUNT) variant = 0;
+    switch (bin * 4 + variant) {
+    case 0: MCL_LAUNCH(128, 1, 4, 2, 4); break;
+    case 1: MCL_LAUNCH(128, 1, 4, 1, 8); break;
+    case 4: MCL_LAUNCH(256, 1, 4, 2, 4); break;
+    case 5: MCL_LAUNCH(256, 1, 4, 1, 8); break;
+    case 8: MCL_LAUNCH(512, 1, 4, 2, 4); break;
+    case 9: MCL_LAUNCH(512, 1, 4, 2, 8); break;
+    case 12: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
+    case 13: MCL_LAUNCH(1024, 2, 1, 1, 8); break;
+    case 14: MCL_LAUNCH(1024, 1, 2, 2, 8); break;
+    case 16: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
+    case 17: MCL_LAUNCH(2048, 4, 1, 1, 8); break;
+    case 18: MCL_LAUNCH(2048, 2, 1, 2, 8); break;
+    case 20: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
+    case 21: MCL_LAUNCH(4096, 8, 1, 1, 8); break;
+    case 22: MCL_LAUNCH(4096, 4, 1, 2, 8); break;
+    case 24: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
+    case 25: MCL_LAUNCH(8192, 16, 1, 1, 8); break;
+    case 26: MCL_LAUNCH(8192, 8, 1, 2, 8); break;
+    default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
+    }
+#undef MCL_LAUNCH
+}
+
+int lds_bin_variants(int bin) { return (bin < 3) ? 2 : 3; }
+
+void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st)
+{
+    if (a.parts) {
+        launch_lds_mode<MODE_EXPAND, true>(bin, 0, a, st);
+        return;
+    }
+    switch (mode) {
+    case MODE_COUNT: launch_lds_mode<MODE_COUNT, false>(bin, 0, a, st); break;
+    case MODE_EXPAND: launch_lds_mode<MODE_EXPAND, false>(bin, variant, a, st); break;
+    case MODE_ITERATE: launch_lds_mode<MODE_ITERATE, false>(bin, variant, a, st); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// HBM-table kernel: persistent workgroups, each with a private slab of
+// device memory holding the table and the sort scratch for one column at a
+// time.  Used for columns whose table does not fit LDS and for the exact
+// count of overflowed columns.
+// ---------------------------------------------------------------------------
+struct SlabLayout {
+    size_t key, val, list, sorted, bcnt, bcur, p0, p1, ip, bytes;
+};
+static __host__ __device__ SlabLayout slab_layout(int S, int cap)
+{
+    const int NB = (S / 4 < 64) ? 64 : S / 4;
+    const int NBLK = cap / WAVE + 2;
+    SlabLayout L;
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += (b + 255) & ~(size_t)255; return r; };
+    L.val = take((size_t)S * 8);
+    L.key = take((size_t)S * 4);
+    L.list = take((size_t)cap * 4);
+    L.sorted = take((size_t)cap * 4);
+    L.bcnt = take((size_t)NB * 4);
+    L.bcur = take((size_t)NB * 4);
+    L.p0 = take((size_t)NBLK * 8);
+    L.p1 = take((size_t)NBLK * 8);
+    L.ip = take((size_t)NBLK * 4);
+    L.bytes = o;
+    return L;
+}
+size_t global_slab_bytes(int S, int cap) { return slab_layout(S, cap).bytes; }
+
+template <int MODE, bool IS_MERGE>
+__global__ __launch_bounds__(1024) void k_numeric_global(NumericArgs a, int S, int cap, char *slab,
+                                                         size_t slab_bytes)
+{
+    constexpr int NT = 1024;
+    __shared__ int32_t hist[256];
+    __shared__ int32_t misc[16];
+    __shared__ double dmisc[4];
+    __shared__ int32_t wsum[NT / WAVE];
+    const SlabLayout L = slab_layout(S, cap);
+    char *my = slab + (size_t)blockIdx.x * slab_bytes;
+    Scratch<int32_t> sc{(int32_t *)(my + L.key), (double *)(my + L.val), (int32_t *)(my + L.list),
+                        (int32_t *)(my + L.sorted), (int *)(my + L.bcnt), (int *)(my + L.bcur),
+                        (double *)(my + L.p0), (double *)(my + L.p1), (int *)(my + L.ip),
+                        hist, misc, dmisc, wsum};
+    const int NB = (S / 4 < 64) ? 64 : S / 4;
+    const int logS = __builtin_ctz((unsigned)S);
+    for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
+        column_body<NT, MODE, 1, 2, int32_t, IS_MERGE, true>(a, a.cols[idx], S, logS, cap, NB, sc);
+        __syncthreads();
+    }
+}
+
+void launch_numeric_global(NumericMode mode, const NumericArgs &a, int S, int cap, void *slab,
+                           size_t slab_bytes, int nslabs, hipStream_t st)
+{
+    if (a.ncols <= 0) return;
+    const int grid = std::min(nslabs, a.ncols);
+    if (a.parts) {
+        hipLaunchKernelGGL((k_numeric_global<MODE_EXPAND, true>), dim3(grid), dim3(1024), 0, st, a, S,
+                           cap, (char *)slab, slab_bytes);
+        return;
+    }
+    switch (mode) {
+    case MODE_COUNT:
+        hipLaunchKernelGGL((k_numeric_global<MODE_COUNT, false>), dim3(grid), dim3(1024), 0, st, a, S,
+                           cap, (char *)slab, slab_bytes);
+        break;
+    case MODE_EXPAND:
+        hipLaunchKernelGGL((k_numeric_global<MODE_EXPAND, false>), dim3(grid), dim3(1024), 0, st, a, S,
+                           cap, (char *)slab, slab_bytes);
+        break;
+    case MODE_ITERATE:
+        hipLaunchKernelGGL((k_numeric_global<MODE_ITERATE, false>), dim3(grid), dim3(1024), 0, st, a,
+                           S, cap, (char *)slab, slab_bytes);
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// overflow list, scans, compaction, batched-mode helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_collect_overflow(const int32_t *__restrict__ cols, int32_t n,
+                                                          const int64_t *__restrict__ cnt,
+                                                          int32_t *__restrict__ list,
+                                                          int32_t *__restrict__ count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int j = cols[i];
+        if (cnt[j] < 0) list[atomicAdd(count, 1)] = j;
+    }
+}
+
+void launch_collect_overflow(int64_t, const int32_t *cols, int32_t n, const int64_t *cnt,
+                             int32_t *ovf_list, int32_t *ovf_count, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_collect_overflow, dim3(grid), dim3(256), 0, st, cols, n, cnt, ovf_list,
+                       ovf_count);
+}
+
+// Exclusive scan of int64 (three phases: per-block sums, scan of the block
+// sums, add back).  out may alias in; out has n+1 entries (out[n] = total).
+constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_ITEMS = 8;
+constexpr int64_t SCAN_TILE = (int64_t)SCAN_BLOCK * SCAN_ITEMS;
+
+__device__ int64_t block_incl_scan_i64(int64_t x, int64_t *ws)
+{
+    const int tid = threadIdx.x, w = tid / WAVE;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, WAVE);
+        if (lane() >= d) x += y;
+    }
+    if (lane() == WAVE - 1) ws[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int64_t v = (lane() < SCAN_BLOCK / WAVE) ? ws[lane()] : 0;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int64_t y = __shfl_up(v, d, WAVE);
+            if (lane() >= d) v += y;
+        }
+        if (lane() < SCAN_BLOCK / WAVE) ws[lane()] = v;
+    }
+    __syncthreads();
+    const int64_t add = (w > 0) ? ws[w - 1] : 0;
+    __syncthreads();
+    return x + add;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_tiles(const int64_t *__restrict__ in, int64_t n,
+                                                           int64_t *__restrict__ tile_sum)
+{
+    __shared__ int64_t ws[SCAN_BLOCK / WAVE];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int64_t s = 0;
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int64_t i = t0 + (int64_t)q * SCAN_BLOCK + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    const int64_t inc = block_incl_scan_i64(s, ws);
+    if (threadIdx.x == SCAN_BLOCK - 1) tile_sum[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int64_t *__restrict__ tile_sum, int64_t ntiles)
+{
+    __shared__ int64_t ws[SCAN_BLOCK / WAVE];
+    __shared__ int64_t last;
+    int64_t carry = 0;
+    for (int64_t b = 0; b < ntiles; b += SCAN_BLOCK) {
+        const int64_t i = b + threadIdx.x;
+        const int64_t v = (i < ntiles) ? tile_sum[i] : 0;
+        const int64_t inc = block_incl_scan_i64(v, ws);
+        if (i < ntiles) tile_sum[i] = carry + inc - v;  // exclusive
+        if (threadIdx.x == SCAN_BLOCK - 1) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[ntiles] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int64_t *__restrict__ in, int64_t n,
+                                                           const int64_t *__restrict__ tile_sum,
+                                                           int64_t *__restrict__ out)
+{
+    __shared__ int64_t ws[SCAN_BLOCK / WAVE];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    // each thread owns SCAN_ITEMS consecutive elements
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int64_t i = t0 + (int64_t)threadIdx.x * SCAN_ITEMS + q;
+        v[q] = (i < n) ? in[i] : 0;
+        s += v[q];
+    }
+    const int64_t inc = block_incl_scan_i64(s, ws);
+    int64_t run = tile_sum[blockIdx.x] + inc - s;
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int64_t i = t0 + (int64_t)threadIdx.x * SCAN_ITEMS + q;
+        if (i < n) out[i] = run;
+        run += v[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) out[n] = tile_sum[gridDim.x];
+}
+
+int64_t exscan_tmp_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 2; }
+
+void launch_exscan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st)
+{
+    const int64_t ntiles = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(SCAN_BLOCK), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, st, tmp, ntiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(SCAN_BLOCK), 0, st, in, n, tmp, out);
+}
+
+// Copy each column's entries from its temp slot to its final position.  One
+// wave per column.
+// Copy every column from its temp slot (region and offset decoded from
+// base) to its final position.  Columns with bin < 0 (inactive) are skipped.
+__global__ __launch_bounds__(256) void k_compact(int64_t ncols, const int32_t *__restrict__ bin,
+                                                 const int64_t *__restrict__ base,
+                                                 const int64_t *__restrict__ cnt,
+                                                 const int64_t *__restrict__ colptr, TempRegions tr,
+                                                 int32_t *__restrict__ row, double *__restrict__ val)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (j >= ncols) return;
+    if (bin && bin[j] < 0) return;
+    const int64_t n = cnt[j];
+    if (n <= 0) return;
+    const int64_t b = base[j], d = colptr[j];
+    int reg = 0;
+    int64_t o = b;
+    if (b < 0) {
+        const int64_t v = -b - 1;
+        reg = (int)(v >> 48);
+        o = v & REGION_MASK;
+    }
+    const int32_t *sr = tr.row[reg] + o;
+    const double *sv = tr.val[reg] + o;
+    for (int64_t q = lane(); q < n; q += WAVE) {
+        row[d + q] = sr[q];
+        val[d + q] = sv[q];
+    }
+}
+
+void launch_compact(int64_t ncols, const int32_t *bin, const int64_t *base, const int64_t *cnt,
+                    const int64_t *colptr, const TempRegions &tr, int32_t *row, double *val,
+                    hipStream_t st)
+{
+    if (ncols == 0) return;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((ncols + 3) / 4)), dim3(256), 0, st, ncols, bin, base,
+                       cnt, colptr, tr, row, val);
+}
+
+// Batched mode: the component of every column and whether it is active.
+__global__ void k_col_comp(int64_t ncols, const int64_t *__restrict__ comp_ptr, int64_t ncomp,
+                           int32_t *__restrict__ col_comp, const uint8_t *__restrict__ active,
+                           uint8_t *__restrict__ col_active)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncomp;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t act = active ? active[c] : 1;
+        for (int64_t j = comp_ptr[c]; j < comp_ptr[c + 1]; ++j) {
+            col_comp[j] = (int32_t)c;
+            col_active[j] = act;
+        }
+    }
+}
+
+void launch_col_comp(int64_t ncols, const int64_t *comp_ptr, int64_t ncomp, int32_t *col_comp,
+                     const uint8_t *active, uint8_t *col_active, hipStream_t st)
+{
+    if (ncomp == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((ncomp + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_col_comp, dim3(grid), dim3(256), 0, st, ncols, comp_ptr, ncomp, col_comp,
+                       active, col_active);
+}
+
+// Inactive (frozen) columns keep their previous entries: count = nnz, change 0.
+__global__ void k_counts_inactive(DevCSC A, const int32_t *__restrict__ col_comp,
+                                  const uint8_t *__restrict__ active, int64_t *__restrict__ cnt,
+                                  double *__restrict__ delta)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < A.ncols;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        if (!active[col_comp[j]]) {
+            cnt[j] = A.colptr[j + 1] - A.colptr[j];
+            delta[j] = 0.0;
+        }
+    }
+}
+
+void launch_counts_inactive(const DevCSC &A, const int32_t *col_comp, const uint8_t *active,
+                            int64_t *cnt, double *delta, hipStream_t st)
+{
+    if (A.ncols == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((A.ncols + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_counts_inactive, dim3(grid), dim3(256), 0, st, A, col_comp, active, cnt, delta);
+}
+
+__global__ __launch_bounds__(256) void k_copy_inactive(DevCSC A, const int32_t *__restrict__ col_comp,
+                                                       const uint8_t *__restrict__ active,
+                                                       const int64_t *__restrict__ colptr,
+                                                       int32_t *__restrict__ row, double *__restrict__ val)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (j >= A.ncols || active[col_comp[j]]) return;
+    const int64_t s = A.colptr[j], n = A.colptr[j + 1] - s, d = colptr[j];
+    for (int64_t q = lane(); q < n; q += WAVE) {
+        row[d + q] = A.rowidx[s + q];
+        val[d + q] = A.val[s + q];
+    }
+}
+
+void launch_copy_inactive(const DevCSC &A, const int32_t *col_comp, const uint8_t *active,
+                          const int64_t *colptr, int32_t *row, double *val, hipStream_t st)
+{
+    if (A.ncols == 0) return;
+    hipLaunchKernelGGL(k_copy_inactive, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A,
+                       col_comp, active, colptr, row, val);
+}
+
+// Per-component max of the per-column change.  One wave per component.
+__global__ __launch_bounds__(256) void k_comp_max(int64_t ncomp, const int64_t *__restrict__ comp_ptr,
+                                                  const double *__restrict__ delta, double *__restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (c >= ncomp) return;
+    double m = 0.0;
+    for (int64_t j = comp_ptr[c] + lane(); j < comp_ptr[c + 1]; j += WAVE) m = fmax(m, delta[j]);
+    m = wave_max(m);
+    if (lane() == 0) out[c] = m;
+}
+
+void launch_comp_max(int64_t ncomp, const int64_t *comp_ptr, const double *delta, double *out,
+                     hipStream_t st)
+{
+    if (ncomp == 0) return;
+    hipLaunchKernelGGL(k_comp_max, dim3((unsigned)((ncomp + 3) / 4)), dim3(256), 0, st, ncomp, comp_ptr,
+                       delta, out);
+}
+
+// CSC invariants: colptr monotone from 0, rows in range and strictly
+// ascending, values finite and > 0.  flag[0] becomes nonzero on a violation.
+__global__ __launch_bounds__(256) void k_validate(DevCSC A, int32_t *__restrict__ flag)
+{
+    const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (j > A.ncols) return;
+    if (j == A.ncols) {
+        if (lane() == 0 && (A.colptr[0] != 0 || A.colptr[A.ncols] != A.nnz)) atomicOr(flag, 1);
+        return;
+    }
+    const int64_t s = A.colptr[j], e = A.colptr[j + 1];
+    bool bad = (e < s) || s < 0 || e > A.nnz;
+    if (!bad) {
+        for (int64_t p = s + lane(); p < e; p += WAVE) {
+            const int r = A.rowidx[p];
+            const double v = A.val[p];
+            if (r < 0 || r >= A.nrows || !(v > 0.0) || !isfinite(v)) bad = true;
+            if (p > s && A.rowidx[p - 1] >= r) bad = true;
+        }
+    }
+    if (__ballot(bad) != 0 && lane() == 0) atomicOr(flag, 1);
+}
+
+void launch_validate(const DevCSC &A, int32_t *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((A.ncols + 1 + 3) / 4)), dim3(256), 0, st, A, flag);
+}
+
+// Totals for the stats block: acc[0] = nnz product, acc[1] = #select,
+// acc[2] = #recover, acc[3] = flops; dmax[0] = max change.
+__global__ __launch_bounds__(256) void k_reduce_stats(int64_t ncols, const int64_t *__restrict__ nnz_prod,
+                                                      const int8_t *__restrict__ mode,
+                                                      const double *__restrict__ delta,
+                                                      const int64_t *__restrict__ flops,
+                                                      unsigned long long *__restrict__ acc,
+                                                      double *__restrict__ dmax)
+{
+    int64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    double dm = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        if (nnz_prod) s0 += nnz_prod[j];
+        if (mode) { s1 += mode[j] == 2; s2 += mode[j] == 1; }
+        if (delta) dm = fmax(dm, delta[j]);
+        if (flops) s3 += flops[j];
+    }
+    s0 = wave_sum_i64(s0);
+    s1 = wave_sum_i64(s1);
+    s2 = wave_sum_i64(s2);
+    s3 = wave_sum_i64(s3);
+    dm = wave_max(dm);
+    if (lane() == 0) {
+        atomicAdd(&acc[0], (unsigned long long)s0);
+        atomicAdd(&acc[1], (unsigned long long)s1);
+        atomicAdd(&acc[2], (unsigned long long)s2);
+        atomicAdd(&acc[3], (unsigned long long)s3);
+        // values are >= 0, so their bit patterns order like the values
+        atomicMax((unsigned long long *)dmax, (unsigned long long)__double_as_longlong(dm));
+    }
+}
+
+void launch_reduce_stats(int64_t ncols, const int64_t *nnz_prod, const int8_t *mode,
+                         const double *delta, const int64_t *flops, int64_t *acc, double *dmax,
+                         hipStream_t st)
+{
+    if (ncols == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_reduce_stats, dim3(grid), dim3(256), 0, st, ncols, nnz_prod, mode, delta, flops,
+                       (unsigned long long *)acc, dmax);
+}
+
+}  // namespace mcl

@@ -1,0 +1,94 @@
+"""Measurement-driven tuner for the per-bin launch shapes and the table
+sizing margin of the expansion kernels.
+
+The numeric phase runs one kernel per table bin, and the library reports
+each bin kernel's time (HIP events).  Launch shapes of different bins are
+independent, so the search is a coordinate descent: for every bin, every
+launch variant is timed with the other bins fixed and the fastest kept; then
+the estimate scale (table sizing margin) is chosen from a short list by the
+whole step time.  Results do not depend on the choice (the accumulation
+order is fixed), only the speed does.  The chosen policy is stored in
+``tuned.json`` next to this file, keyed by workload name.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNED = os.path.join(HERE, "tuned.json")
+VARIANTS = [2, 2, 2, 3, 3, 3, 3]        # launch variants per LDS bin
+SCALES = (1.0, 1.25, 1.5, 2.0)
+
+
+def pack(variants) -> int:
+    return sum((int(v) & 15) << (4 * b) for b, v in enumerate(variants))
+
+
+def unpack(policy: int):
+    return [(policy >> (4 * b)) & 15 for b in range(len(VARIANTS))]
+
+
+def load_policy(key: str, default=(0, 1.0)):
+    try:
+        with open(TUNED) as f:
+            d = json.load(f)
+        e = d[key]
+        return int(e["bin_policy"], 0), float(e["est_scale"])
+    except (OSError, KeyError, ValueError):
+        return default
+
+
+def save_policy(key: str, policy: int, scale: float, info: dict):
+    d = {}
+    if os.path.exists(TUNED):
+        with open(TUNED) as f:
+            d = json.load(f)
+    d[key] = dict(bin_policy=hex(policy), est_scale=scale, **info)
+    with open(TUNED, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+
+
+def tune(run, reps=2, log=print):
+    """run(policy, scale) -> stats dict of one step (bin_ms, t_total_ms).
+    Returns (policy, scale, report)."""
+    import torch
+
+    def measure(policy, scale):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = run(policy, scale)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) * 1e3
+            if best is None or dt < best[0]:
+                best = (dt, st)
+        return best
+
+    variants = [0] * len(VARIANTS)
+    scale = 1.0
+    report = {"bins": {}}
+    base_ms, base_st = measure(pack(variants), scale)
+    report["start_ms"] = base_ms
+    for b in range(len(VARIANTS)):
+        times = []
+        for v in range(VARIANTS[b]):
+            trial = list(variants)
+            trial[b] = v
+            ms, st = measure(pack(trial), scale)
+            times.append(st["bin_ms"][b])
+        if st["bin_cols"][b] == 0:
+            continue
+        variants[b] = min(range(len(times)), key=lambda v: times[v])
+        report["bins"][b] = [round(t, 3) for t in times]
+        log("bin %d variant times %s -> %d" % (b, report["bins"][b], variants[b]))
+    best_scale, best_ms = scale, None
+    for sc in SCALES:
+        ms, st = measure(pack(variants), sc)
+        log("scale %.2f: %.1f ms (overflow %d)" % (sc, ms, st["n_overflow"]))
+        if best_ms is None or ms < best_ms:
+            best_scale, best_ms = sc, ms
+    report["final_ms"] = best_ms
+    return pack(variants), best_scale, report
