@@ -35,6 +35,10 @@ constexpr int64_t REGION_MASK = ((int64_t)1 << 48) - 1;
 // (load factor 3/4; more keys flag the column as overflowed).
 __host__ __device__ constexpr int bin_slots_c(int b) { return 128 << b; }
 __host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4; }
+// Keys a column may be planned with in bin b: bins of 1024+ slots split the
+// column over waves with private tables, so they keep 1/8 headroom for an
+// uneven spread of rows over the waves.
+__host__ __device__ constexpr int plan_cap_c(int b) { return (b >= 3) ? (bin_cap_c(b) * 7) / 8 : bin_cap_c(b); }
 int lds_bin_slots(int bin) { return bin_slots_c(bin); }
 int lds_bin_cap(int bin) { return bin_cap_c(bin); }
 
@@ -276,15 +280,15 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
         ub = min(ub, nrows);
         int64_t need = ub;
         bool try_lds = false;
-        if (est_kind != 0 && est && ub > bin_cap_c(3)) {
+        if (est_kind != 0 && est && ub > plan_cap_c(2)) {
             double e = ceil(1.3 * est_scale * (double)est[j]);
             if (e < 1.0) e = 1.0;
             need = min(ub, (int64_t)e);
             // an estimate near the largest LDS table still tries LDS first
-            try_lds = (double)est[j] <= 1.25 * bin_cap_c(NUM_LDS_BINS - 1);
+            try_lds = (double)est[j] <= 1.25 * plan_cap_c(NUM_LDS_BINS - 1);
         }
         int b = 0;
-        while (b < NUM_LDS_BINS && bin_cap_c(b) < need) ++b;
+        while (b < NUM_LDS_BINS && plan_cap_c(b) < need) ++b;
         if (b == NUM_LDS_BINS && try_lds) b = NUM_LDS_BINS - 1;
         bin[j] = b;
         capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
@@ -346,8 +350,8 @@ void launch_bound_estimate(int64_t n, const int64_t *flops, const int32_t *lo, c
     hipLaunchKernelGGL(k_bound_estimate, dim3(grid), dim3(256), 0, st, n, flops, lo, hi, nrows, est);
 }
 
-// Re-plan of overflowed columns from their exact product size m_j: the
-// smallest LDS bin that holds m_j, else the HBM table sized for m_j.
+// Re-plan of columns that overflowed the largest LDS bin, from their exact
+// product size m_j: the HBM table sized for m_j.
 __global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list, int32_t n,
                                                 const int64_t *__restrict__ exact,
                                                 int32_t *__restrict__ bin, int64_t *__restrict__ capv,
@@ -356,13 +360,12 @@ __global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int j = list[i];
-        const int64_t need = exact[j];
-        int b = 0;
-        while (b < NUM_LDS_BINS && bin_cap_c(b) < need) ++b;
+        const int64_t need = max(exact[j], (int64_t)1);
+        const int b = NUM_LDS_BINS;
         bin[j] = b;
-        capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
+        capv[j] = need;
         atomicAdd(&bin_count[b], 1);
-        if (b == NUM_LDS_BINS) atomicMax(max_global, (unsigned long long)need);
+        atomicMax(max_global, (unsigned long long)need);
     }
 }
 
@@ -682,6 +685,144 @@ __device__ void prune_decide(Get get, int m, const PruneArgs &pa, double *p0, do
     *out_t = t;
 }
 
+// Sort the m keys of a table (S slots) by row: bucket count over the row
+// span [lo, lo+span), prefix sum, scatter of slot ids into bucket order, then
+// the rank of every key inside its bucket by comparison.  emit(rank, slot)
+// is called once per key.  Called by all NT threads of the group.
+template <int NT, bool GS, typename IdxT, typename Emit>
+__device__ void sort_table(const int32_t *tkey, int S, int m, int32_t lo, int64_t span, int *bcnt,
+                           int *bcur, int NB, IdxT *list, int *wsum, Emit emit)
+{
+    const int tid = threadIdx.x % NT;
+    const uint64_t mul = (span <= NB) ? (1ull << 32) : (((uint64_t)NB << 32) / (uint64_t)span);
+    for (int b = tid; b < NB; b += NT) bcnt[b] = 0;
+    group_sync<NT, GS>();
+    for (int s = tid; s < S; s += NT) {
+        const int k = tkey[s];
+        if (k != EMPTY_KEY) atomicAdd(&bcnt[bucket_of(k, lo, mul, NB)], 1);
+    }
+    group_sync<NT, GS>();
+    block_exscan<NT, GS>(bcnt, NB, wsum);
+    for (int b = tid; b < NB; b += NT) bcur[b] = bcnt[b];
+    group_sync<NT, GS>();
+    for (int s = tid; s < S; s += NT) {
+        const int k = tkey[s];
+        if (k != EMPTY_KEY) {
+            const int pos = atomicAdd(&bcur[bucket_of(k, lo, mul, NB)], 1);
+            list[pos] = (IdxT)s;
+        }
+    }
+    group_sync<NT, GS>();
+    for (int p = tid; p < m; p += NT) {
+        const int s = list[p];
+        const int k = tkey[s];
+        const int b = bucket_of(k, lo, mul, NB);
+        const int st = bcnt[b];
+        const int en = (b + 1 < NB) ? bcnt[b + 1] : m;
+        int rank = st;
+        for (int q = st; q < en; ++q) rank += (tkey[list[q]] < k) ? 1 : 0;
+        emit(rank, s);
+    }
+}
+
+// Fused-iteration epilogue on a table whose m keys are listed in row order in
+// sc.sorted: prune (Alg. 1), inflation with column re-normalisation, the
+// change against the previous iterate (column j of B, which is A), and the
+// per-column outputs.  find(row) returns the slot of a row or -1.
+template <int NT, bool GS, typename IdxT, typename Find>
+__device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t bs, int mj,
+                                 int64_t base, const int32_t *tkey, double *tval,
+                                 const Scratch<IdxT> &sc, Find find)
+{
+    const int tid = threadIdx.x % NT;
+    const int w = tid / WAVE;
+    constexpr int NWV = (NT + WAVE - 1) / WAVE;
+    // ---------------- prune (Alg. 1) ----------------
+    auto getv = [&](int p) { return tval[sc.sorted[p]]; };
+    int pmode;
+    double t;
+    prune_decide<NT, GS>(getv, m, a.pa, sc.p0, sc.p1, sc.ip, sc.hist, sc.misc, sc.dmisc, &pmode, &t);
+
+    // kept entries, in row order, into sc.list
+    const int nblk = (m + WAVE - 1) / WAVE;
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const bool keep = (p < m) && (getv(p) >= t);
+        const int c = __popcll(ballot(keep));
+        if (lane() == 0) sc.ip[b] = c;
+    }
+    group_sync<NT, GS>();
+    const int K = block_exscan<NT, GS>(sc.ip, nblk, sc.wsum);
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const bool keep = (p < m) && (getv(p) >= t);
+        const uint64_t mk = ballot(keep);
+        if (keep) sc.list[sc.ip[b] + popc_below(mk)] = sc.sorted[p];
+    }
+    group_sync<NT, GS>();
+
+    // ---------------- inflation: c^r / column sum (fixed tree over kept rank) ----------------
+    const double r = a.pa.r;
+    const int kblk = (K + WAVE - 1) / WAVE;
+    for (int b = w; b < kblk; b += NWV) {
+        const int q = b * WAVE + lane();
+        const double c = (q < K) ? inflate_pow(tval[sc.list[q]], r) : 0.0;
+        const double bsum = wave_sum(c);
+        if (lane() == 0) sc.p0[b] = bsum;
+    }
+    group_sync<NT, GS>();
+    if (tid < WAVE) {
+        const double ssum = fixed_tree_finish(sc.p0, kblk);
+        if (lane() == 0) sc.dmisc[1] = ssum;
+    }
+    // dropped entries read as 0 in the change computation
+    for (int p = tid; p < m; p += NT) {
+        const int s = sc.sorted[p];
+        if (tval[s] < t) tval[s] = 0.0;
+    }
+    group_sync<NT, GS>();
+    const double ssum = sc.dmisc[1];
+    for (int q = tid; q < K; q += NT) {
+        const int s = sc.list[q];
+        const double c = inflate_pow(tval[s], r);
+        const double an = (ssum > 0.0) ? c / ssum : 0.0;
+        a.out_row[base + q] = tkey[s];
+        a.out_val[base + q] = an;
+        tval[s] = an;
+    }
+    group_sync<NT, GS>();
+
+    // ---------------- change vs the previous iterate (A_*j == B_*j) ----------------
+    double dmax = 0.0;
+    for (int t2 = tid; t2 < mj; t2 += NT) {
+        const int k = a.B.rowidx[bs + t2];
+        const double old = a.B.val[bs + t2];
+        const int s = find(k);
+        if (s >= 0) {
+            dmax = fmax(dmax, fabs(tval[s] - old));
+            tval[s] = -1.0;  // matched
+        } else {
+            dmax = fmax(dmax, old);
+        }
+    }
+    group_sync<NT, GS>();
+    for (int q = tid; q < K; q += NT) dmax = fmax(dmax, tval[sc.list[q]]);  // unmatched new entries
+    dmax = wave_max(dmax);
+    if constexpr (NT > WAVE) {
+        if (lane() == 0) sc.p1[w] = dmax;
+        group_sync<NT, GS>();
+        if (tid == 0) {
+            for (int q = 1; q < NWV; ++q) dmax = fmax(dmax, sc.p1[q]);
+        }
+    }
+    if (tid == 0) {
+        a.out_cnt[j] = K;
+        if (a.nnz_prod) a.nnz_prod[j] = m;
+        if (a.delta) a.delta[j] = dmax;
+        if (a.mode) a.mode[j] = (int8_t)pmode;
+    }
+}
+
 // The numeric body for one column j, executed by NT threads.
 template <int NT, int MODE, int E, int D, typename IdxT, bool IS_MERGE, bool GS>
 __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, int cap, int NB,
@@ -772,10 +913,12 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
             ioff = more ? ioff + CH : 0;
             iu = more ? iu : iu + 1;
         };
+        // Burst groups: the loads of D consecutive chunks are issued back to
+        // back, then the chunks are folded in order (one memory latency per
+        // group; other waves and workgroups on the CU overlap it).
+        for (int g0 = 0; g0 < total && !overflow; g0 += D) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) issue(rr[i], vv[i], vb[i], bb[i]);
-        const int rounds = (total + D - 1) / D;
-        for (int rd = 0; rd < rounds; ++rd) {
+            for (int i = 0; i < D; ++i) issue(rr[i], vv[i], vb[i], bb[i]);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
 #pragma unroll
@@ -787,9 +930,8 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
                     }
                 }
                 group_sync<NT, GS>();
-                overflow = sc.misc[1] != 0;
-                issue(rr[i], vv[i], vb[i], bb[i]);
             }
+            overflow = sc.misc[1] != 0;
         }
     }
     group_sync<NT, GS>();
@@ -806,131 +948,21 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
     // ---------------- sort the m keys by row ----------------
     const int32_t lo = a.lo[j];
     const int64_t span = (int64_t)a.hi[j] - lo + 1;
-    const uint64_t mul = (span <= NB) ? (1ull << 32) : (((uint64_t)NB << 32) / (uint64_t)span);
-    for (int b = tid; b < NB; b += NT) sc.bcnt[b] = 0;
-    group_sync<NT, GS>();
-    for (int s = tid; s < S; s += NT) {
-        const int k = tkey[s];
-        if (k != EMPTY_KEY) atomicAdd(&sc.bcnt[bucket_of(k, lo, mul, NB)], 1);
-    }
-    group_sync<NT, GS>();
-    block_exscan<NT, GS>(sc.bcnt, NB, sc.wsum);
-    for (int b = tid; b < NB; b += NT) sc.bcur[b] = sc.bcnt[b];
-    group_sync<NT, GS>();
-    for (int s = tid; s < S; s += NT) {
-        const int k = tkey[s];
-        if (k != EMPTY_KEY) {
-            const int pos = atomicAdd(&sc.bcur[bucket_of(k, lo, mul, NB)], 1);
-            sc.list[pos] = (IdxT)s;
-        }
-    }
-    group_sync<NT, GS>();
     const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
-    for (int p = tid; p < m; p += NT) {
-        const int s = sc.list[p];
-        const int k = tkey[s];
-        const int b = bucket_of(k, lo, mul, NB);
-        const int st = sc.bcnt[b];
-        const int en = (b + 1 < NB) ? sc.bcnt[b + 1] : m;
-        int rank = st;
-        for (int q = st; q < en; ++q) rank += (tkey[sc.list[q]] < k) ? 1 : 0;
-        if (MODE == MODE_EXPAND) {
-            a.out_row[base + rank] = k;
-            a.out_val[base + rank] = tval[s];
-        } else {
-            sc.sorted[rank] = (IdxT)s;
-        }
-    }
     if (MODE == MODE_EXPAND) {
+        sort_table<NT, GS, IdxT>(tkey, S, m, lo, span, sc.bcnt, sc.bcur, NB, sc.list, sc.wsum,
+                                 [&](int rank, int s) {
+                                     a.out_row[base + rank] = tkey[s];
+                                     a.out_val[base + rank] = tval[s];
+                                 });
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
+    sort_table<NT, GS, IdxT>(tkey, S, m, lo, span, sc.bcnt, sc.bcur, NB, sc.list, sc.wsum,
+                             [&](int rank, int s) { sc.sorted[rank] = (IdxT)s; });
     group_sync<NT, GS>();
-
-    // ---------------- prune (Alg. 1) ----------------
-    auto getv = [&](int p) { return tval[sc.sorted[p]]; };
-    int pmode;
-    double t;
-    prune_decide<NT, GS>(getv, m, a.pa, sc.p0, sc.p1, sc.ip, sc.hist, sc.misc, sc.dmisc, &pmode, &t);
-
-    // kept entries, in row order, into sc.list
-    const int nblk = (m + WAVE - 1) / WAVE;
-    for (int b = w; b < nblk; b += NWV) {
-        const int p = b * WAVE + lane();
-        const bool keep = (p < m) && (getv(p) >= t);
-        const int c = __popcll(ballot(keep));
-        if (lane() == 0) sc.ip[b] = c;
-    }
-    group_sync<NT, GS>();
-    const int K = block_exscan<NT, GS>(sc.ip, nblk, sc.wsum);
-    for (int b = w; b < nblk; b += NWV) {
-        const int p = b * WAVE + lane();
-        const bool keep = (p < m) && (getv(p) >= t);
-        const uint64_t mk = ballot(keep);
-        if (keep) sc.list[sc.ip[b] + popc_below(mk)] = sc.sorted[p];
-    }
-    group_sync<NT, GS>();
-
-    // ---------------- inflation: c^r / column sum (fixed tree over kept rank) ----------------
-    const double r = a.pa.r;
-    const int kblk = (K + WAVE - 1) / WAVE;
-    for (int b = w; b < kblk; b += NWV) {
-        const int q = b * WAVE + lane();
-        const double c = (q < K) ? inflate_pow(tval[sc.list[q]], r) : 0.0;
-        const double bsum = wave_sum(c);
-        if (lane() == 0) sc.p0[b] = bsum;
-    }
-    group_sync<NT, GS>();
-    if (tid < WAVE) {
-        const double ssum = fixed_tree_finish(sc.p0, kblk);
-        if (lane() == 0) sc.dmisc[1] = ssum;
-    }
-    // dropped entries read as 0 in the change computation
-    for (int p = tid; p < m; p += NT) {
-        const int s = sc.sorted[p];
-        if (tval[s] < t) tval[s] = 0.0;
-    }
-    group_sync<NT, GS>();
-    const double ssum = sc.dmisc[1];
-    for (int q = tid; q < K; q += NT) {
-        const int s = sc.list[q];
-        const double c = inflate_pow(tval[s], r);
-        const double an = (ssum > 0.0) ? c / ssum : 0.0;
-        a.out_row[base + q] = tkey[s];
-        a.out_val[base + q] = an;
-        tval[s] = an;
-    }
-    group_sync<NT, GS>();
-
-    // ---------------- change vs the previous iterate (A_*j == B_*j) ----------------
-    double dmax = 0.0;
-    for (int t2 = tid; t2 < mj; t2 += NT) {
-        const int k = a.B.rowidx[bs + t2];
-        const double old = a.B.val[bs + t2];
-        const int s = find_slot(tkey, k, logS, mask);
-        if (s >= 0) {
-            dmax = fmax(dmax, fabs(tval[s] - old));
-            tval[s] = -1.0;  // matched
-        } else {
-            dmax = fmax(dmax, old);
-        }
-    }
-    group_sync<NT, GS>();
-    for (int q = tid; q < K; q += NT) dmax = fmax(dmax, tval[sc.list[q]]);  // unmatched new entries
-    dmax = wave_max(dmax);
-    if constexpr (NT > WAVE) {
-        if (lane() == 0) sc.p1[w] = dmax;
-        group_sync<NT, GS>();
-        if (tid == 0) {
-            for (int q = 1; q < NWV; ++q) dmax = fmax(dmax, sc.p1[q]);
-        }
-    }
-    if (tid == 0) {
-        a.out_cnt[j] = K;
-        if (a.nnz_prod) a.nnz_prod[j] = m;
-        if (a.delta) a.delta[j] = dmax;
-        if (a.mode) a.mode[j] = (int8_t)pmode;
-    }
+    iterate_epilogue<NT, GS, IdxT>(a, j, m, bs, mj, base, tkey, tval, sc,
+                                   [&](int32_t k) { return find_slot(tkey, k, logS, mask); });
 }
 
 // ---------------------------------------------------------------------------
@@ -972,6 +1004,281 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
     column_body<NT, MODE, E, D, uint16_t, IS_MERGE, false>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
 }
 
+// ---------------------------------------------------------------------------
+// Split-table kernel for large columns: NW waves per column, wave w owning
+// the rows of one slice [rlo_w, rhi_w) of the column's row span and a private
+// table of SW slots.  A_*k has ascending rows, so each wave fetches only the
+// slice of every A_*k that can hold its rows: the window comes from linear
+// interpolation between the first and last row of A_*k, widened by SLACK
+// entries and then verified (the entries just outside the window must lie
+// outside the slice; otherwise the window is extended).  Waves never touch
+// each other's rows, so accumulation needs no barrier, each wave keeps
+// ascending-k order for its rows, and a wave skips every A_*k whose row range
+// misses its slice.  The column's sorted order is the concatenation of the
+// waves' sorted slices.
+// ---------------------------------------------------------------------------
+constexpr int SPLIT_SLACK = 16;
+
+template <int NW, int SW, int MODE, int D, bool IS_MERGE>
+__global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
+{
+    constexpr int NT = NW * WAVE;
+    constexpr int CAPW = (3 * SW) / 4;
+    constexpr int NBW = (SW / 4 < 64) ? 64 : SW / 4;
+    constexpr int STOT = NW * SW;
+    constexpr int CAPT = NW * CAPW;
+    constexpr int NBLK = CAPT / WAVE + 2;
+    constexpr int LOGSW = __builtin_ctz(SW);
+    static_assert(STOT <= 65536, "slot ids are 16-bit");
+    struct Sh {
+        double val[STOT];
+        int32_t key[STOT];
+        double p0[NBLK], p1[NBLK];
+        int32_t ip[NBLK];
+        int32_t bcnt[NW * NBW], bcur[NW * NBW];
+        int32_t hist[256];
+        uint16_t list[CAPT], sorted[CAPT];
+        int32_t wcnt[NW], wovf[NW];
+        int32_t misc[16];
+        double dmisc[4];
+        int32_t wsum[NW];
+    };
+    __shared__ Sh sh;
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    const int64_t j = a.cols[blockIdx.x];
+    int32_t *wkey = sh.key + w * SW;
+    double *wval = sh.val + w * SW;
+    for (int s = lane(); s < SW; s += WAVE) {
+        wkey[s] = EMPTY_KEY;
+        if (MODE != MODE_COUNT) wval[s] = 0.0;
+    }
+    if (lane() == 0) { sh.wcnt[w] = 0; sh.wovf[w] = 0; }
+    group_sync<WAVE>();
+
+    const int32_t lo = a.lo[j];
+    const int64_t span = (int64_t)a.hi[j] - lo + 1;
+    // owner(row) = floor((row - lo) * NW / span); slice w = [rlo, rhi)
+    const int32_t rlo = lo + (int32_t)(((int64_t)w * span + NW - 1) / NW);
+    const int32_t rhi = lo + (int32_t)(((int64_t)(w + 1) * span + NW - 1) / NW);
+    const int32_t *dummy_r = (const int32_t *)a.dummy;
+    const double *dummy_v = (const double *)a.dummy;
+
+    const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
+    const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
+    bool overflow = false;
+
+    // fold entries [c0, min(c0+64, cend)) of one source column into the slice
+    auto fold = [&](const int32_t *rr, const double *vv, double b, int c0, int cend, int32_t &row0,
+                    int32_t &rowl) {
+        const int e = c0 + lane();
+        const bool in = e < cend;
+        const int32_t row = ldg(in ? rr + e : dummy_r);
+        double v = 0.0;
+        if (MODE != MODE_COUNT) v = ldg(in ? vv + e : dummy_v);
+        if (in && row >= rlo && row < rhi) {
+            const int s = find_or_insert(wkey, row, LOGSW, SW - 1, &sh.wcnt[w], CAPW, &sh.wovf[w]);
+            if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(v, b, wval[s]);
+        }
+        group_sync<WAVE>();
+        row0 = readlane_i(row, 0);
+        rowl = readlane_i(row, min(WAVE - 1, max(0, cend - 1 - c0)));
+    };
+
+    for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
+        // lane l describes step tb + l: source column pointers, length, b,
+        // first/last row, and this wave's window [ws, we) in it
+        const int t = tb + lane();
+        const int32_t *rp = nullptr;
+        const double *vp = nullptr;
+        int klen = 0;
+        double bv = 1.0;
+        if (t < mj) {
+            if constexpr (IS_MERGE) {
+                const DevCSC &P = a.parts[t];
+                const int64_t p0 = P.colptr[j];
+                rp = P.rowidx + p0;
+                vp = P.val + p0;
+                klen = (int)(P.colptr[j + 1] - p0);
+            } else {
+                const int k = a.B.rowidx[bs + t];
+                bv = a.B.val[bs + t];
+                const int64_t p0 = a.A.colptr[k];
+                rp = a.A.rowidx + p0;
+                vp = a.A.val + p0;
+                klen = (int)(a.A.colptr[k + 1] - p0);
+            }
+        }
+        int ws = 0, we = 0;
+        if (klen > 0) {
+            const int32_t fr = ldg(rp), lr = ldg(rp + klen - 1);
+            if (!(rhi <= fr || rlo > lr)) {
+                const float sc = (float)klen / (float)((int64_t)lr - fr + 1);
+                const int g0 = (rlo <= fr) ? 0 : (int)((float)(rlo - fr) * sc);
+                const int g1 = (rhi > lr) ? klen : (int)((float)(rhi - fr) * sc);
+                ws = (rlo <= fr) ? 0 : max(0, g0 - SPLIT_SLACK);
+                we = (rhi > lr) ? klen : min(klen, g1 + SPLIT_SLACK);
+                if (we <= ws) { ws = max(0, min(ws, klen - 1)); we = ws + 1; }
+            }
+        }
+        const int nch = (we - ws + WAVE - 1) / WAVE;        // chunks of this step's window
+        const int cpre = wave_incl_scan(nch) - nch;          // chunks before this step
+        const int total = readlane_i(cpre + nch, WAVE - 1);
+        // chunk c of the batch -> (step, chunk within the step's window)
+        auto locate = [&](int c, int &u, int &ic) {
+            const uint64_t m = ballot(nch > 0 && cpre <= c);
+            u = (m != 0) ? 63 - __clzll(m) : 0;
+            ic = c - readlane_i(cpre, u);
+        };
+        int32_t frow = 0;
+        // After the last chunk of step u: verify its window and extend it
+        // while rows of the slice may lie outside (entries of one step have
+        // distinct rows, so their order does not matter).
+        auto extend = [&](int u, int ic, int wsu, int weu, double b, int32_t lrow) {
+            (void)ic;
+            const int L = readlane_i(klen, u);
+            const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, u);
+            const double *vb = (const double *)readlane_i64((int64_t)vp, u);
+            int cws = wsu, cwe = weu;
+            int32_t r0 = frow, rl = lrow;
+            while (cws > 0 && r0 >= rlo) {
+                const int n0 = max(0, cws - WAVE);
+                int32_t x0, xl;
+                fold(rb, vb, b, n0, cws, x0, xl);
+                r0 = x0;
+                cws = n0;
+            }
+            while (cwe < L && rl < rhi) {
+                const int n1 = min(L, cwe + WAVE);
+                int32_t x0, xl;
+                fold(rb, vb, b, cwe, n1, x0, xl);
+                rl = xl;
+                cwe = n1;
+            }
+        };
+        // Burst groups: the loads of D consecutive chunks are issued back to
+        // back, then the chunks are folded in order.  One memory latency is
+        // paid per group; the other waves of the CU overlap it.
+        const int32_t *dmy_r = dummy_r;
+        for (int g0 = 0; g0 < total && !overflow; g0 += D) {
+            int32_t rr_[D];
+            double vv_[D];
+            bool in_[D];
+            int su[D], sic[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int c = g0 + i;
+                locate(c, su[i], sic[i]);
+                const int u = su[i];
+                const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, u);
+                const double *vb = (const double *)readlane_i64((int64_t)vp, u);
+                const int c0 = readlane_i(ws, u) + sic[i] * WAVE;
+                const int ce = readlane_i(we, u);
+                const int e = c0 + lane();
+                in_[i] = (c < total) && e < ce;
+                rr_[i] = ldg(in_[i] ? rb + e : dmy_r);
+                if (MODE != MODE_COUNT) vv_[i] = ldg(in_[i] ? vb + e : dummy_v);
+            }
+            // Does any window completed in this group need an extension?
+            // (register-only check; the common answer is no, and then the
+            // group is folded by a straight-line path without extra loads)
+            bool any_ext = false;
+            {
+                int32_t fr_c = frow;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const int c = g0 + i;
+                    const int u = su[i], ic = sic[i];
+                    if (c < total) {
+                        const int wsu = readlane_i(ws, u), weu = readlane_i(we, u);
+                        if (ic == 0) fr_c = readlane_i(rr_[i], 0);
+                        if (ic == readlane_i(nch, u) - 1) {
+                            const int32_t lr_c = readlane_i(rr_[i], min(WAVE - 1, weu - 1 - (wsu + ic * WAVE)));
+                            any_ext |= (wsu > 0 && fr_c >= rlo) || (weu < readlane_i(klen, u) && lr_c < rhi);
+                        }
+                    }
+                }
+            }
+            if (!any_ext) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const double b = readlane_d(bv, su[i]);
+                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
+                        const int s = find_or_insert(wkey, rr_[i], LOGSW, SW - 1, &sh.wcnt[w], CAPW,
+                                                     &sh.wovf[w]);
+                        if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(vv_[i], b, wval[s]);
+                    }
+                    group_sync<WAVE>();
+                    if (g0 + i < total && sic[i] == 0) frow = readlane_i(rr_[i], 0);
+                }
+            } else {
+                for (int i = 0; i < D; ++i) {
+                    const int c = g0 + i;
+                    const int u = su[i], ic = sic[i];
+                    const double b = readlane_d(bv, u);
+                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
+                        const int s = find_or_insert(wkey, rr_[i], LOGSW, SW - 1, &sh.wcnt[w], CAPW,
+                                                     &sh.wovf[w]);
+                        if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(vv_[i], b, wval[s]);
+                    }
+                    group_sync<WAVE>();
+                    if (c < total) {
+                        const int wsu = readlane_i(ws, u), weu = readlane_i(we, u);
+                        if (ic == 0) frow = readlane_i(rr_[i], 0);
+                        if (ic == readlane_i(nch, u) - 1)
+                            extend(u, ic, wsu, weu, b,
+                                   readlane_i(rr_[i], min(WAVE - 1, weu - 1 - (wsu + ic * WAVE))));
+                    }
+                }
+            }
+            overflow = sh.wovf[w] != 0;
+        }
+    }
+    __syncthreads();  // every slice is complete (LDS and the wave flags)
+
+    int m = 0, off = 0, ovf = 0;
+    for (int q = 0; q < NW; ++q) {
+        const int c = sh.wcnt[q];
+        if (q < w) off += c;
+        m += c;
+        ovf |= sh.wovf[q];
+    }
+    if (ovf) {
+        if (tid == 0) a.out_cnt[j] = -1;
+        return;
+    }
+    if (MODE == MODE_COUNT) {
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    const int mw = sh.wcnt[w];
+    uint16_t *wlist = sh.list + w * CAPW;
+    if (MODE == MODE_EXPAND) {
+        sort_table<WAVE, false, uint16_t>(wkey, SW, mw, rlo, (int64_t)rhi - rlo, sh.bcnt + w * NBW,
+                                          sh.bcur + w * NBW, NBW, wlist, &sh.wsum[w],
+                                          [&](int rank, int s) {
+                                              a.out_row[base + off + rank] = wkey[s];
+                                              a.out_val[base + off + rank] = wval[s];
+                                          });
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+    sort_table<WAVE, false, uint16_t>(wkey, SW, mw, rlo, (int64_t)rhi - rlo, sh.bcnt + w * NBW,
+                                      sh.bcur + w * NBW, NBW, wlist, &sh.wsum[w],
+                                      [&](int rank, int s) { sh.sorted[off + rank] = (uint16_t)(w * SW + s); });
+    __syncthreads();
+    Scratch<uint16_t> sc{sh.key, sh.val, sh.list, sh.sorted, sh.bcnt, sh.bcur, sh.p0, sh.p1,
+                         sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
+    const int32_t hi = a.hi[j];
+    iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, sh.key, sh.val, sc, [&](int32_t k) {
+        if (k < lo || k > hi) return -1;
+        const int ow = (int)(((int64_t)(k - lo) * NW) / span);
+        const int s = find_slot(sh.key + ow * SW, k, LOGSW, SW - 1);
+        return (s < 0) ? -1 : ow * SW + s;
+    });
+}
+
 // Launch shapes per bin: (waves per column, columns per workgroup, entries
 // per lane per chunk, chunks in flight).  Variant 0 is the default; the
 // others are alternatives the tuner may select through mcl_params.bin_policy
@@ -984,7 +1291,10 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 #define MCL_LAUNCH(S_, NW_, CPW_, E_, D_)                                                   \
     hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE>),              \
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
-    if (IS_MERGE || MODE == MODE_COUNT) variant = 0;
+    if (MODE == MODE_COUNT) variant = 0;
+#define MCL_SPLIT(NW_, D_)                                                                   \
+    hipLaunchKernelGGL((k_numeric_split<NW_, 512, MODE, D_, IS_MERGE>), dim3(n), dim3(NW_ * WAVE), 0, \
+                       st, a)
     switch (bin * 4 + variant) {
     case 0: MCL_LAUNCH(128, 1, 4, 2, 4); break;
     case 1: MCL_LAUNCH(128, 1, 4, 1, 8); break;
@@ -992,20 +1302,21 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 5: MCL_LAUNCH(256, 1, 4, 1, 8); break;
     case 8: MCL_LAUNCH(512, 1, 4, 2, 4); break;
     case 9: MCL_LAUNCH(512, 1, 4, 2, 8); break;
-    case 12: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
-    case 13: MCL_LAUNCH(1024, 2, 1, 1, 8); break;
-    case 14: MCL_LAUNCH(1024, 1, 2, 2, 8); break;
-    case 16: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
-    case 17: MCL_LAUNCH(2048, 4, 1, 1, 8); break;
-    case 18: MCL_LAUNCH(2048, 2, 1, 2, 8); break;
-    case 20: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
-    case 21: MCL_LAUNCH(4096, 8, 1, 1, 8); break;
-    case 22: MCL_LAUNCH(4096, 4, 1, 2, 8); break;
-    case 24: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
-    case 25: MCL_LAUNCH(8192, 16, 1, 1, 8); break;
-    case 26: MCL_LAUNCH(8192, 8, 1, 2, 8); break;
+    case 12: MCL_SPLIT(2, 4); break;
+    case 13: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
+    case 14: MCL_SPLIT(2, 8); break;
+    case 16: MCL_SPLIT(4, 4); break;
+    case 17: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
+    case 18: MCL_SPLIT(4, 8); break;
+    case 20: MCL_SPLIT(8, 4); break;
+    case 21: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
+    case 22: MCL_SPLIT(8, 8); break;
+    case 24: MCL_SPLIT(16, 4); break;
+    case 25: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
+    case 26: MCL_SPLIT(16, 8); break;
     default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
     }
+#undef MCL_SPLIT
 #undef MCL_LAUNCH
 }
 

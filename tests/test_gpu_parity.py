@@ -41,7 +41,7 @@ def assert_same_matrix(g: CSC, o: CSC, exact=True, rtol=0.0):
 
 # ---------------------------------------------------------------- expansion
 
-@pytest.mark.parametrize("case", ["rect", "skew", "empty", "planted", "dense_cols"])
+@pytest.mark.parametrize("case", ["rect", "skew", "empty", "planted", "dense_cols", "bigcluster"])
 def test_expand_bit_exact(mcl, case):
     print("case", case, flush=True)
     if case == "rect":
@@ -55,6 +55,9 @@ def test_expand_bit_exact(mcl, case):
         B = random_csc(80, 60, 3, seed=6)
     elif case == "planted":
         A = oracle.normalize(planted_graph(6000, 200, s_cap=600, seed=7))
+        B = A
+    elif case == "bigcluster":   # product columns up to ~6000 rows: the largest LDS bins
+        A = oracle.normalize(planted_graph(40000, 2000, s_cap=2100, seed=70))
         B = A
     else:  # a few very long columns -> large tables / HBM-table path
         A = random_csc(40000, 600, 400, seed=8)
@@ -167,6 +170,28 @@ def test_iterate_parity_config0(mcl, seed):
 def test_iterate_parity_small_k(mcl, S, R, theta):
     A = oracle.normalize(planted_graph(5000, 180, s_cap=500, seed=17))
     check_iterate(mcl, A, theta=theta, S=S, R=R)
+
+
+ALL_VARIANTS = [0x0, 0x1111111, 0x2222222, 0x2222010]
+
+
+def test_launch_variants_are_bit_identical(mcl):
+    A = oracle.normalize(planted_graph(40000, 2000, s_cap=2100, seed=71))
+    dA = up(mcl, A)
+    ref, c0, st0 = mcl.iterate(dA, bin_policy=0)
+    assert max(st0["bin_cols"][4:7]) > 0
+    E0, _ = mcl.expand(dA, dA, bin_policy=0)
+    for pol in ALL_VARIANTS[1:]:
+        X, c1, _ = mcl.iterate(dA, bin_policy=pol)
+        assert torch.equal(X.rowidx, ref.rowidx) and torch.equal(X.val, ref.val) and c1 == c0
+        E1, _ = mcl.expand(dA, dA, bin_policy=pol)
+        assert torch.equal(E1.rowidx, E0.rowidx) and torch.equal(E1.val, E0.val)
+
+
+def test_iterate_parity_big_clusters(mcl):
+    A = oracle.normalize(planted_graph(40000, 2000, s_cap=2100, seed=72))
+    _, _, st = check_iterate(mcl, A)
+    assert st["bin_cols"][6] > 0
 
 
 def test_iterate_is_composition_of_exports(mcl):
