@@ -90,16 +90,30 @@ void gen_assemble(int64_t n, int64_t E, const int32_t *eu, const int32_t *ev, co
                   int64_t *colptr, int32_t *rowidx, double *val)
 {
     int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    for (int64_t e = 0; e < E; ++e) { deg[eu[e]]++; deg[ev[e]]++; }
+    #pragma omp parallel for schedule(static)
+    for (int64_t e = 0; e < E; ++e) {
+        #pragma omp atomic
+        deg[eu[e]]++;
+        #pragma omp atomic
+        deg[ev[e]]++;
+    }
     colptr[0] = 0;
     for (int64_t j = 0; j < n; ++j) colptr[j + 1] = colptr[j] + deg[j] + 1;
     int64_t *cur = deg;
     for (int64_t j = 0; j < n; ++j) cur[j] = colptr[j];
     rw_t *tmp = (rw_t *)malloc(sizeof(rw_t) * (size_t)(colptr[n] > 0 ? colptr[n] : 1));
+    /* placement inside a column depends on the thread schedule; the per-column
+       sort below makes the result independent of it (rows are unique) */
+    #pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < E; ++e) {
+        int64_t pa, pb;
+        #pragma omp atomic capture
+        pa = cur[eu[e]]++;
+        #pragma omp atomic capture
+        pb = cur[ev[e]]++;
         rw_t a = { ev[e], 0, ew[e] }, b = { eu[e], 0, ew[e] };
-        tmp[cur[eu[e]]++] = a;        /* column eu[e], row ev[e] */
-        tmp[cur[ev[e]]++] = b;
+        tmp[pa] = a;        /* column eu[e], row ev[e] */
+        tmp[pb] = b;
     }
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t j = 0; j < n; ++j) {

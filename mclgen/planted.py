@@ -158,6 +158,33 @@ def _rescale_to_total(sizes: np.ndarray, total: int, s_min: int) -> np.ndarray:
     return base
 
 
+def _rescale_groups(sizes: np.ndarray, group: np.ndarray, totals: np.ndarray, s_min) -> np.ndarray:
+    """Vectorised largest-remainder rescale of every group of ``sizes`` (group
+    ids ascending, contiguous) to sum to totals[group]; each size >= s_min[group]
+    where possible (the clamp excess is taken from the group's largest)."""
+    sizes = sizes.astype(np.float64)
+    ng = len(totals)
+    gsum = np.bincount(group, weights=sizes, minlength=ng)
+    f = sizes * (totals / gsum)[group]
+    base = np.floor(f).astype(np.int64)
+    rem = totals - np.bincount(group, weights=base, minlength=ng).astype(np.int64)
+    order = np.lexsort((-(f - base), group))
+    start = np.zeros(ng + 1, np.int64)
+    start[1:] = np.cumsum(np.bincount(group, minlength=ng))
+    rank = np.empty(len(sizes), np.int64)
+    rank[order] = np.arange(len(sizes)) - start[group[order]]
+    base += (rank < rem[group]).astype(np.int64)
+    smin = np.broadcast_to(np.asarray(s_min), (ng,))[group]
+    base = np.maximum(base, smin)
+    excess = np.bincount(group, weights=base, minlength=ng).astype(np.int64) - totals
+    if (excess > 0).any():
+        big = np.lexsort((-base, group))          # largest first within each group
+        first = big[start[:-1][start[:-1] < start[1:]]]
+        gi = group[first]
+        base[first] -= np.maximum(excess[gi], 0)
+    return base
+
+
 def _expected_nnz_per_col(sizes, n, p_in, x):
     m_in = p_in * float(np.sum(sizes * (sizes - 1) / 2.0))
     m_x = x / (1.0 - x) * m_in
@@ -286,17 +313,12 @@ def planted_components(comp_sizes: Sequence[int], comp_clusters: Sequence[int], 
     comp_ptr = np.zeros(ncomp + 1, np.int64)
     comp_ptr[1:] = np.cumsum(comp_sizes)
 
-    # 1. cluster sizes per component
-    sizes_l, ccomp_l = [], []
-    for c in range(ncomp):
-        k = int(comp_clusters[c])
-        smin = min(s_min, int(comp_sizes[c]) // max(k, 1)) or 1
-        u = rng.random(k)
-        sz = powerlaw_sizes(u, alpha, smin, max(s_cap, smin + 1))
-        sizes_l.append(_rescale_to_total(sz, int(comp_sizes[c]), smin))
-        ccomp_l.append(np.full(k, c, np.int64))
-    sizes = np.concatenate(sizes_l)
-    ccomp = np.concatenate(ccomp_l)
+    # 1. cluster sizes per component (one shared power law, rescaled per component)
+    ccomp = np.repeat(np.arange(ncomp), comp_clusters)
+    smin_c = np.maximum(1, np.minimum(s_min, comp_sizes // np.maximum(comp_clusters, 1)))
+    u = rng.random(len(ccomp))
+    raw = powerlaw_sizes(u, alpha, s_min, max(s_cap, s_min + 1))
+    sizes = _rescale_groups(raw, ccomp, comp_sizes, smin_c)
     cstart = np.zeros(len(sizes) + 1, np.int64)
     cstart[1:] = np.cumsum(sizes)          # cluster ranges in position space
     pos_cluster = np.repeat(np.arange(len(sizes)), sizes)
@@ -328,11 +350,10 @@ def planted_components(comp_sizes: Sequence[int], comp_clusters: Sequence[int], 
     span = comp_sizes[xc]
     u = lo + (rng.random(len(xc)) * span).astype(np.int64)
     v = lo + (rng.random(len(xc)) * span).astype(np.int64)
-    bad = pos_cluster[u] == pos_cluster[v]
-    while bad.any():
-        idx = np.nonzero(bad)[0]
+    idx = np.nonzero(pos_cluster[u] == pos_cluster[v])[0]
+    while len(idx):
         v[idx] = lo[idx] + (rng.random(len(idx)) * span[idx]).astype(np.int64)
-        bad = pos_cluster[u] == pos_cluster[v]
+        idx = idx[pos_cluster[u[idx]] == pos_cluster[v[idx]]]
     wx = w_x * (1.0 - rng.random(len(xc)))      # in (0, w_x]
     xu, xv = perm[u], perm[v]
     lo_v, hi_v = np.minimum(xu, xv), np.maximum(xu, xv)
@@ -397,18 +418,13 @@ def config3_graph(seed=1003, n_comp=20_000, total=4_000_000, smin_comp=8, smax_c
     ccl = np.maximum(1, np.rint(csz / 25.0)).astype(np.int64)
     if s_cap is None:
         u2 = np.random.Generator(np.random.PCG64(seed + 7919)).random(int(ccl.sum()))
-        # fit on the pooled cluster-size distribution, rescaled per component
+        grp = np.repeat(np.arange(n_comp), ccl)
+        smin_c = np.maximum(1, np.minimum(3, csz // ccl))
         lo, hi = 4, 30000
         while hi - lo > 1:
             mid = (lo + hi) // 2
-            sizes = []
-            off = 0
-            for c in range(n_comp):
-                k = int(ccl[c])
-                sizes.append(_rescale_to_total(powerlaw_sizes(u2[off:off + k], 2.0, 3, mid),
-                                               int(csz[c]), min(3, int(csz[c]) // k)))
-                off += k
-            d = _expected_nnz_per_col(np.concatenate(sizes), int(csz.sum()), 0.3, 0.05)
+            sizes = _rescale_groups(powerlaw_sizes(u2, 2.0, 3, mid), grp, csz, smin_c)
+            d = _expected_nnz_per_col(sizes, int(csz.sum()), 0.3, 0.05)
             if d < target_nnz_per_col:
                 lo = mid
             else:

@@ -311,7 +311,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     }
     {
         int64_t *dummy = mem.ws<int64_t>(8);
-        HIPC(hipMemsetAsync(dummy, 0, 8 * sizeof(int64_t), mem.st));
+        HIPC(hipMemsetAsync(dummy, 0xFF, 8 * sizeof(int64_t), mem.st));  // row -1 (no row)
         a.dummy = dummy;
     }
     a.lo = pl.lo;

@@ -538,42 +538,102 @@ struct Scratch {
     int *wsum;       // NT/64 ints for scans
 };
 
-// Find row `key` in the open-addressing table or insert it.  A new key first
-// reserves one unit of the capacity counter, so the table never holds more
-// than `cap` < S keys and probing always terminates.  Returns the slot, or -1
-// (and raises the overflow flag) when the capacity is exhausted.
-__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logS, int mask, int *nkeys,
-                                              int cap, int *ovf)
+// Open-addressing table of S slots organised as S/4 buckets of four int32
+// keys (16-byte aligned).  A key lives in the first bucket, starting at its
+// home bucket, that had a free slot when it was inserted; one 128-bit LDS read
+// fetches a whole bucket, so a lookup is normally one read and four compares,
+// and an insertion one compare-and-swap.  Probing stops after PROBE_MAX
+// bucket visits: the key is then reported as not placed (-1, overflow flag
+// raised) and the column is recomputed with a larger table.
+constexpr int PROBE_MAX = 16;
+typedef int32_t keys4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) keys4 lds_keys4;  // tables live in LDS
+
+__device__ __forceinline__ int bucket_match(const keys4 kb, int32_t k)
 {
-    uint32_t h = hash_slot(k, logS);
-    for (;;) {
-        const int cur = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == k) return (int)h;
-        if (cur == EMPTY_KEY) {
-            const int r = atomicAdd(nkeys, 1);
-            if (r >= cap) {
-                atomicSub(nkeys, 1);
-                *ovf = 1;
-                return -1;
-            }
-            const int old = atomicCAS(&key[h], EMPTY_KEY, k);
-            if (old == EMPTY_KEY) return (int)h;
-            atomicSub(nkeys, 1);
-            if (old == k) return (int)h;
-        }
-        h = (h + 1) & (uint32_t)mask;
+    return (kb.x == k) ? 0 : (kb.y == k) ? 1 : (kb.z == k) ? 2 : (kb.w == k) ? 3 : -1;
+}
+
+__device__ __forceinline__ int bucket_empty(const keys4 kb)
+{
+    return (kb.x == EMPTY_KEY) ? 0 : (kb.y == EMPTY_KEY) ? 1 : (kb.z == EMPTY_KEY) ? 2
+         : (kb.w == EMPTY_KEY) ? 3 : -1;
+}
+
+// Read bucket b.  LDS tables use one 128-bit LDS read; tables in HBM (the
+// largest columns) read the four words as workgroup-scope atomics, so slots
+// claimed by other waves of the workgroup are seen.
+template <bool LDS>
+__device__ __forceinline__ keys4 load_bucket(const int32_t *key, uint32_t b)
+{
+    if constexpr (LDS) {
+        return *(volatile const lds_keys4 *)(key + 4 * b);
+    } else {
+        keys4 r;
+        int32_t *p = const_cast<int32_t *>(key + 4 * b);
+        r.x = __hip_atomic_load(p + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        r.y = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        r.z = __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        r.w = __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return r;
     }
 }
 
-__device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logS, int mask)
+template <bool LDS>
+__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB, int nbmask, int *ovf)
 {
-    uint32_t h = hash_slot(k, logS);
-    for (;;) {
-        const int cur = key[h];
-        if (cur == k) return (int)h;
-        if (cur == EMPTY_KEY) return -1;
-        h = (h + 1) & (uint32_t)mask;
+    uint32_t b = hash_slot(k, logNB);
+#pragma unroll 1
+    for (int p = 0; p < PROBE_MAX; ++p) {
+        const keys4 kb = load_bucket<LDS>(key, b);
+        const int hit = bucket_match(kb, k);
+        if (hit >= 0) return (int)(4 * b) + hit;
+        const int e = bucket_empty(kb);
+        if (e < 0) {
+            b = (b + 1) & (uint32_t)nbmask;
+            continue;
+        }
+        const int old = atomicCAS(&key[4 * b + e], EMPTY_KEY, k);
+        if (old == EMPTY_KEY || old == k) return (int)(4 * b) + e;
+        // another key took that slot: look at the same bucket again
     }
+    *ovf = 1;
+    return -1;
+}
+
+// Lookup after all insertions (and a barrier): plain reads suffice.
+template <bool LDS>
+__device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logNB, int nbmask)
+{
+    uint32_t b = hash_slot(k, logNB);
+#pragma unroll 1
+    for (int p = 0; p < PROBE_MAX; ++p) {
+        keys4 kb;
+        if constexpr (LDS) kb = *(const lds_keys4 *)(key + 4 * b);
+        else kb = *(const keys4 *)(key + 4 * b);
+        const int hit = bucket_match(kb, k);
+        if (hit >= 0) return (int)(4 * b) + hit;
+        if (bucket_empty(kb) >= 0) return -1;
+        b = (b + 1) & (uint32_t)nbmask;
+    }
+    return -1;
+}
+
+// Number of occupied slots (called by all NT threads; result to all).
+template <int NT, bool GS>
+__device__ int count_keys(const int32_t *tkey, int S, int *acc)
+{
+    const int tid = threadIdx.x % NT;
+    int c = 0;
+    for (int s = tid; s < S; s += NT) c += (tkey[s] != EMPTY_KEY) ? 1 : 0;
+    c = wave_sum_i(c);
+    if (tid == 0) *acc = 0;
+    group_sync<NT, GS>();
+    if (lane() == 0) atomicAdd(acc, c);
+    group_sync<NT, GS>();
+    const int m = *acc;
+    group_sync<NT, GS>();
+    return m;
 }
 
 __device__ __forceinline__ int bucket_of(int32_t k, int32_t lo, uint64_t mul, int NB)
@@ -829,9 +889,6 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
                            const Scratch<IdxT> &sc)
 {
     const int tid = threadIdx.x % NT;
-    const int w = tid / WAVE;
-    constexpr int NWV = (NT + WAVE - 1) / WAVE;
-    const int mask = S - 1;
     if (a.capv) cap = (int)min((int64_t)cap, a.capv[j]);
     int32_t *tkey = sc.key;
     double *tval = sc.val;
@@ -881,21 +938,18 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         constexpr int CH = NT * E;
         const int nchunk_l = (lane() < nb) ? max(1, (klen + CH - 1) / CH) : 0;
         const int total = wave_sum_i(nchunk_l);
-        // Ring of D chunks in flight: chunk c+D is requested right after
-        // chunk c has been folded into the table, so D-1 chunks of loads
-        // overlap every table update.  Chunks are consumed in load order,
-        // which keeps the ascending-k accumulation order.  Every load is
-        // issued unconditionally (lanes past the end read a valid dummy
-        // word and carry a cleared validity bit) and the iterator advances
-        // with selects, so the compiler can keep the loads outstanding.
+        // Chunks are consumed in load order, which keeps the ascending-k
+        // accumulation order.  Every load is issued unconditionally (lanes
+        // past the end read a dummy word holding row -1) and the iterator
+        // advances with selects, so the compiler can keep the loads
+        // outstanding.
         const int32_t *dummy_r = (const int32_t *)a.dummy;
         const double *dummy_v = (const double *)a.dummy;
         int iu = 0, ioff = 0;
         int32_t rr[D][E];
         double vv[D][E];
-        bool vb[D][E];
         double bb[D];
-        auto issue = [&](int32_t(&r)[E], double(&v)[E], bool(&in)[E], double &b) {
+        auto issue = [&](int32_t(&r)[E], double(&v)[E], double &b) {
             const int ul = min(iu, WAVE - 1);
             const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, ul);
             const double *vbp = (const double *)readlane_i64((int64_t)vp, ul);
@@ -905,9 +959,9 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
 #pragma unroll
             for (int q = 0; q < E; ++q) {
                 const int e = ioff + tid + q * NT;
-                in[q] = e < len;
-                r[q] = ldg(in[q] ? rb + e : dummy_r);
-                if (MODE != MODE_COUNT) v[q] = ldg(in[q] ? vbp + e : dummy_v);
+                const bool in = e < len;
+                r[q] = ldg(in ? rb + e : dummy_r);
+                if (MODE != MODE_COUNT) v[q] = ldg(in ? vbp + e : dummy_v);
             }
             const bool more = ioff + CH < len;
             ioff = more ? ioff + CH : 0;
@@ -918,15 +972,23 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         // group; other waves and workgroups on the CU overlap it).
         for (int g0 = 0; g0 < total && !overflow; g0 += D) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) issue(rr[i], vv[i], vb[i], bb[i]);
+            for (int i = 0; i < D; ++i) issue(rr[i], vv[i], bb[i]);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
-                    if (vb[i][q] && !overflow) {
-                        const int s = find_or_insert(tkey, rr[i][q], logS, mask, &sc.misc[0], cap,
-                                                     &sc.misc[1]);
-                        if (MODE != MODE_COUNT && s >= 0) tval[s] = fma(vv[i][q], bb[i], tval[s]);
+                    // the dummy word reads as row -1; testing the loaded
+                    // row (not a separate flag) keeps the load ahead of the
+                    // branch, so the compiler cannot sink it into the branch
+                    int s = -1;
+                    if (rr[i][q] >= 0 && !overflow)
+                        s = find_or_insert<!GS>(tkey, rr[i][q], logS - 2, (S >> 2) - 1, &sc.misc[1]);
+                    if (MODE != MODE_COUNT) {
+                        // unconditional update (idle lanes hit a spare word
+                        // that accumulation does not otherwise use), so the
+                        // value load is not sunk into a branch either
+                        double *dst = (s >= 0) ? tval + s : sc.p0;
+                        *dst = fma(vv[i][q], bb[i], *dst);
                     }
                 }
                 group_sync<NT, GS>();
@@ -935,8 +997,8 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         }
     }
     group_sync<NT, GS>();
-    const int m = sc.misc[0];
-    if (sc.misc[1]) {
+    const int m = count_keys<NT, GS>(tkey, S, &sc.misc[0]);
+    if (sc.misc[1] || m > cap) {
         if (tid == 0) a.out_cnt[j] = -1;
         return;
     }
@@ -962,7 +1024,7 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
                              [&](int rank, int s) { sc.sorted[rank] = (IdxT)s; });
     group_sync<NT, GS>();
     iterate_epilogue<NT, GS, IdxT>(a, j, m, bs, mj, base, tkey, tval, sc,
-                                   [&](int32_t k) { return find_slot(tkey, k, logS, mask); });
+                                   [&](int32_t k) { return find_slot<!GS>(tkey, k, logS - 2, (S >> 2) - 1); });
 }
 
 // ---------------------------------------------------------------------------
@@ -981,7 +1043,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 {
     using L = LdsBin<S>;
     constexpr int NT = NW * WAVE;
-    struct Col {
+    struct alignas(16) Col {
         double val[S];
         int32_t key[S];
         double p0[L::NBLK], p1[L::NBLK];
@@ -993,7 +1055,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
         double dmisc[4];
         int32_t wsum[NW];
     };
-    __shared__ Col cols[CPW];
+    __shared__ Col cols[CPW] __attribute__((aligned(16)));
     const int ci = threadIdx.x / NT;
     const int64_t idx = (int64_t)blockIdx.x * CPW + ci;
     if (idx >= a.ncols) return;  // whole groups exit together
@@ -1030,7 +1092,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     constexpr int NBLK = CAPT / WAVE + 2;
     constexpr int LOGSW = __builtin_ctz(SW);
     static_assert(STOT <= 65536, "slot ids are 16-bit");
-    struct Sh {
+    struct alignas(16) Sh {
         double val[STOT];
         int32_t key[STOT];
         double p0[NBLK], p1[NBLK];
@@ -1043,7 +1105,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
         double dmisc[4];
         int32_t wsum[NW];
     };
-    __shared__ Sh sh;
+    __shared__ Sh sh __attribute__((aligned(16)));
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     const int64_t j = a.cols[blockIdx.x];
@@ -1077,7 +1139,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
         double v = 0.0;
         if (MODE != MODE_COUNT) v = ldg(in ? vv + e : dummy_v);
         if (in && row >= rlo && row < rhi) {
-            const int s = find_or_insert(wkey, row, LOGSW, SW - 1, &sh.wcnt[w], CAPW, &sh.wovf[w]);
+            const int s = find_or_insert<true>(wkey, row, LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
             if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(v, b, wval[s]);
         }
         group_sync<WAVE>();
@@ -1203,10 +1265,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
                     const double b = readlane_d(bv, su[i]);
-                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
-                        const int s = find_or_insert(wkey, rr_[i], LOGSW, SW - 1, &sh.wcnt[w], CAPW,
-                                                     &sh.wovf[w]);
-                        if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(vv_[i], b, wval[s]);
+                    int s = -1;
+                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi)
+                        s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
+                    if (MODE != MODE_COUNT) {
+                        // idle lanes update a spare word of their wave
+                        double *dst = (s >= 0) ? wval + s : &sh.p0[w];
+                        *dst = fma(vv_[i], b, *dst);
                     }
                     group_sync<WAVE>();
                     if (g0 + i < total && sic[i] == 0) frow = readlane_i(rr_[i], 0);
@@ -1217,8 +1282,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
                     const int u = su[i], ic = sic[i];
                     const double b = readlane_d(bv, u);
                     if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
-                        const int s = find_or_insert(wkey, rr_[i], LOGSW, SW - 1, &sh.wcnt[w], CAPW,
-                                                     &sh.wovf[w]);
+                        const int s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
                         if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(vv_[i], b, wval[s]);
                     }
                     group_sync<WAVE>();
@@ -1232,6 +1296,16 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
                 }
             }
             overflow = sh.wovf[w] != 0;
+        }
+    }
+    {
+        // keys of this wave's slice; more than its capacity means overflow
+        int c = 0;
+        for (int q = lane(); q < SW; q += WAVE) c += (wkey[q] != EMPTY_KEY) ? 1 : 0;
+        c = wave_sum_i(c);
+        if (lane() == 0) {
+            sh.wcnt[w] = c;
+            if (c > CAPW) sh.wovf[w] = 1;
         }
     }
     __syncthreads();  // every slice is complete (LDS and the wave flags)
@@ -1274,7 +1348,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, sh.key, sh.val, sc, [&](int32_t k) {
         if (k < lo || k > hi) return -1;
         const int ow = (int)(((int64_t)(k - lo) * NW) / span);
-        const int s = find_slot(sh.key + ow * SW, k, LOGSW, SW - 1);
+        const int s = find_slot<true>(sh.key + ow * SW, k, LOGSW - 2, SW / 4 - 1);
         return (s < 0) ? -1 : ow * SW + s;
     });
 }
@@ -1295,32 +1369,44 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 #define MCL_SPLIT(NW_, D_)                                                                   \
     hipLaunchKernelGGL((k_numeric_split<NW_, 512, MODE, D_, IS_MERGE>), dim3(n), dim3(NW_ * WAVE), 0, \
                        st, a)
-    switch (bin * 4 + variant) {
+    switch (bin * 8 + variant) {
     case 0: MCL_LAUNCH(128, 1, 4, 2, 4); break;
     case 1: MCL_LAUNCH(128, 1, 4, 1, 8); break;
-    case 4: MCL_LAUNCH(256, 1, 4, 2, 4); break;
-    case 5: MCL_LAUNCH(256, 1, 4, 1, 8); break;
-    case 8: MCL_LAUNCH(512, 1, 4, 2, 4); break;
-    case 9: MCL_LAUNCH(512, 1, 4, 2, 8); break;
-    case 12: MCL_SPLIT(2, 4); break;
-    case 13: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
-    case 14: MCL_SPLIT(2, 8); break;
-    case 16: MCL_SPLIT(4, 4); break;
-    case 17: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
-    case 18: MCL_SPLIT(4, 8); break;
-    case 20: MCL_SPLIT(8, 4); break;
-    case 21: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
-    case 22: MCL_SPLIT(8, 8); break;
-    case 24: MCL_SPLIT(16, 4); break;
-    case 25: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
-    case 26: MCL_SPLIT(16, 8); break;
+    case 8: MCL_LAUNCH(256, 1, 4, 2, 4); break;
+    case 9: MCL_LAUNCH(256, 1, 4, 1, 8); break;
+    case 16: MCL_LAUNCH(512, 1, 4, 2, 4); break;
+    case 17: MCL_LAUNCH(512, 1, 4, 2, 8); break;
+    case 24: MCL_SPLIT(2, 4); break;
+    case 25: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
+    case 26: MCL_SPLIT(2, 8); break;
+    case 27: MCL_LAUNCH(1024, 1, 2, 4, 4); break;
+    case 32: MCL_SPLIT(4, 4); break;
+    case 33: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
+    case 34: MCL_SPLIT(4, 8); break;
+    case 35: MCL_LAUNCH(2048, 2, 1, 4, 4); break;
+    case 36: MCL_LAUNCH(2048, 4, 1, 2, 8); break;
+    case 40: MCL_SPLIT(8, 4); break;
+    case 41: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
+    case 42: MCL_SPLIT(8, 8); break;
+    case 43: MCL_LAUNCH(4096, 4, 1, 2, 8); break;
+    case 44: MCL_LAUNCH(4096, 2, 1, 4, 8); break;
+    case 48: MCL_SPLIT(16, 4); break;
+    case 49: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
+    case 50: MCL_SPLIT(16, 8); break;
+    case 51: MCL_LAUNCH(8192, 4, 1, 2, 8); break;
+    case 52: MCL_LAUNCH(8192, 2, 1, 4, 8); break;
+    case 53: MCL_LAUNCH(8192, 8, 1, 1, 8); break;
     default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
     }
 #undef MCL_SPLIT
 #undef MCL_LAUNCH
 }
 
-int lds_bin_variants(int bin) { return (bin < 3) ? 2 : 3; }
+int lds_bin_variants(int bin)
+{
+    static const int nv[NUM_LDS_BINS] = {2, 2, 2, 4, 5, 5, 6};
+    return (bin >= 0 && bin < NUM_LDS_BINS) ? nv[bin] : 1;
+}
 
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st)
 {

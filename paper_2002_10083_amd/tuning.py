@@ -18,7 +18,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-VARIANTS = [2, 2, 2, 3, 3, 3, 3]        # launch variants per LDS bin
+VARIANTS = [2, 2, 2, 4, 5, 5, 6]        # launch variants per LDS bin
 SCALES = (1.0, 1.25, 1.5, 2.0)
 
 
