@@ -31,6 +31,28 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_FLOP, BYTES_PER_BNZ, BYTES_PER_OUT, BYTES_PER_COL = 12, 28, 12, 8
 
 
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_numeric_lds_cfg1.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_10083_amd", "csrc", "spgemm.hip")
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when
+    the summary is missing, is for another kernel, or the kernel source has
+    changed since it was taken."""
+    import hashlib
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l and not l.startswith("#"))
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("source_sha256") != sha or kv.get("kernel_key") != kernel_key:
+        return None
+    return int(float(kv["hbm_bytes_per_launch"]))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -77,6 +99,8 @@ def main():
                     help="bin launch policy (default: tuned table if present)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -96,11 +120,17 @@ def main():
     mcl.normalize_(A)
     torch.cuda.synchronize()
     est = mcl.EST_COHEN if args.estimator == "cohen" else mcl.EST_BOUND
-    policy, scale = tuning.load_policy("iterate", default=(0, 1.0))
+    policy, scale, keys = tuning.load_policy("iterate")
     if args.policy is not None:
         policy = args.policy
-    params = mcl.default_params(estimator=est, bin_policy=policy, est_scale=scale)
+    params = mcl.default_params(estimator=est, bin_policy=policy, est_scale=scale, cohen_keys=keys)
 
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         G, _, st = mcl.iterate(A, params)
         del G
@@ -126,8 +156,11 @@ def main():
     byt = bin_bytes(sts[0], dom)
     achieved = byt / (mean_ms[dom] * 1e-3) / 1e9
     name = ("k_numeric_lds<%d slots>" % (128 << dom)) if dom < 7 else "k_numeric_global"
+    variant = (policy >> (4 * dom)) & 15 if dom < 7 else 0
+    kernel_key = "bin%d-v%d-keys%d" % (dom, variant, keys)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel_key),
+            "kernel": name, "kernel_key": kernel_key,
             "kernel_ms": round(mean_ms[dom], 3), "algorithmic_bytes": int(byt)}
     total_bytes = sum(bin_bytes(sts[0], b) for b in range(nb))
     numeric_ms = float(np.mean([s["t_numeric_ms"] for s in sts]))
@@ -140,7 +173,7 @@ def main():
         "config": {"workload": "one fused MCL iteration (expand+prune/select/recover+inflate) on a "
                                "planted-cluster graph, n=%d, ~100 nnz/col, seed 1001" % W.ncols,
                    "n": W.ncols, "nnz": W.nnz, "flops": flops, "estimator": args.estimator,
-                   "bin_policy": hex(policy), "est_scale": scale,
+                   "bin_policy": hex(policy), "est_scale": scale, "cohen_keys": keys,
                    "prune": "theta=1e-4 S=1100 R=1400 pct=0.9 r=2"},
         "output_nnz_per_s": round(nnz_prod * args.steps / dt, 1),
         "kept_nnz_per_s": round(kept * args.steps / dt, 1),

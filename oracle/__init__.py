@@ -112,7 +112,8 @@ def expand(A: CSC, B: CSC):
     """C = A B (Alg. 1 expansion).  Returns (C, flops_per_col, nnz_per_col).
 
     Column j of C accumulates b_kj * A_*k for the nonzeros of B_*j in ascending
-    k, each entry as fma(a_ik, b_kj, acc); flops_j = sum_{k in B_*j} nnz(A_*k)
+    k, each entry as acc + a_ik * b_kj (rounded product, then a rounded add,
+    the semiring update of the expansion); flops_j = sum_{k in B_*j} nnz(A_*k)
     (Section 2, "Notations")."""
     if A.ncols != B.nrows:
         raise ValueError("shape mismatch")

@@ -83,8 +83,9 @@ void orc_expand_count(int64_t a_nrows, int64_t b_ncols,
 }
 
 /* Pass 2: values.  For column j, the nonzeros b_kj are visited in ascending k
- * and every a_ik of column k is accumulated as spa[i] = fma(a_ik, b_kj, spa[i])
- * (the first touch of row i starts from 0.0).  The touched rows are then
+ * and every a_ik of column k is accumulated as spa[i] = spa[i] + a_ik * b_kj
+ * (the product rounded to double, then added; the first touch of row i starts
+ * from 0.0; built without floating-point contraction).  The touched rows are then
  * sorted ascending.  c_colptr must hold the exclusive prefix sum of pass 1. */
 void orc_expand_fill(int64_t a_nrows, int64_t b_ncols,
                      const int64_t *a_colptr, const int32_t *a_rowidx, const double *a_val,
@@ -107,7 +108,7 @@ void orc_expand_fill(int64_t a_nrows, int64_t b_ncols,
                 for (int64_t q = a_colptr[k]; q < a_colptr[k + 1]; ++q) {
                     int32_t i = a_rowidx[q];
                     if (stamp[i] != j) { stamp[i] = j; spa[i] = 0.0; touched[cnt++] = i; }
-                    spa[i] = fma(a_val[q], bkj, spa[i]);
+                    spa[i] = spa[i] + a_val[q] * bkj;
                 }
             }
             qsort(touched, (size_t)cnt, sizeof(int32_t), cmp_i32);

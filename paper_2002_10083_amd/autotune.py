@@ -13,6 +13,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--key", default="iterate")
+    ap.add_argument("--copy-to", default=None, help="also write the table to this file")
     args = ap.parse_args()
     import torch
     from mclgen import config1_graph
@@ -21,17 +22,19 @@ def main():
     A = mcl.DeviceCSC.from_host(W)
     mcl.normalize_(A)
 
-    def run(policy, scale):
-        G, _, st = mcl.iterate(A, bin_policy=policy, est_scale=scale)
+    def run(policy, scale, keys):
+        G, _, st = mcl.iterate(A, bin_policy=policy, est_scale=scale, cohen_keys=keys)
         del G
         return st
 
     t = time.time()
-    policy, scale, rep = tuning.tune(run)
+    policy, scale, keys, rep = tuning.tune(run)
     rep["tune_s"] = round(time.time() - t, 1)
     rep["gpu"] = torch.cuda.get_device_name(0)
-    tuning.save_policy(args.key, policy, scale, rep)
-    print("tuned", hex(policy), scale, rep, flush=True)
+    tuning.save_policy(args.key, policy, scale, keys, rep)
+    if args.copy_to:
+        tuning.save_policy(args.key, policy, scale, keys, rep, path=args.copy_to)
+    print("tuned", hex(policy), scale, keys, rep, flush=True)
 
 
 if __name__ == "__main__":

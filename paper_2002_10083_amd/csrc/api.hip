@@ -608,6 +608,7 @@ int mcl_expand(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, const mcl_params 
         a.A = dA;
         a.B = dB;
         a.pa = prune_args(p);
+        a.xcd_order = p.schedule & MCL_SCHED_XCD;
         EngineOut eo;
         engine(mem, n, A->nrows, mcl::MODE_EXPAND, a, pl, eo, tm, B->colptr, (uint32_t)p.bin_policy);
         if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, pl.cnt, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
@@ -685,6 +686,7 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
         a.nnz_prod = nnzp;
         a.delta = delta;
         a.mode = mode;
+        a.xcd_order = p.schedule & MCL_SCHED_XCD;
         EngineOut eo;
         engine(mem, n, A->nrows, mcl::MODE_ITERATE, a, pl, eo, tm, A->colptr, (uint32_t)p.bin_policy);
         if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);

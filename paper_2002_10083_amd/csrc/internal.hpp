@@ -42,6 +42,7 @@ struct NumericArgs {
     const DevCSC *parts;      // merge mode: device array of nparts matrices (else null)
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
+    int32_t xcd_order;        // nonzero: contiguous runs of the column list per XCD
 };
 
 // ---- spgemm.hip

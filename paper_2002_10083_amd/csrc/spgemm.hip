@@ -12,8 +12,10 @@
 // table of S slots (int32 row key + fp64 value) in LDS.  The nonzeros of B_*j
 // are visited in ascending k and, for each, all entries of A_*k are inserted
 // in parallel: rows inside one A_*k are distinct, so a k-step has no
-// conflicts, and k-steps are separated by a barrier.  Every output entry is
-// therefore accumulated as acc = fma(a_ik, b_kj, acc) in ascending k no
+// conflicts, and k-steps are separated by a barrier (or owned by a single
+// wave, whose LDS operations complete in issue order).  Every output entry is
+// therefore accumulated as acc = acc + (a_ik * b_kj) (product rounded to
+// double, then one rounded add) in ascending k no
 // matter how the table is laid out -- results are bit-identical across table
 // sizes, bins and schedules.  The column is then sorted by row (bucket count
 // + in-bucket rank) and either written (expand) or pruned, inflated and
@@ -542,12 +544,28 @@ struct Scratch {
 // keys (16-byte aligned).  A key lives in the first bucket, starting at its
 // home bucket, that had a free slot when it was inserted; one 128-bit LDS read
 // fetches a whole bucket, so a lookup is normally one read and four compares,
-// and an insertion one compare-and-swap.  Probing stops after PROBE_MAX
-// bucket visits: the key is then reported as not placed (-1, overflow flag
-// raised) and the column is recomputed with a larger table.
-constexpr int PROBE_MAX = 16;
+// and an insertion one compare-and-swap.  In LDS tables probing stops after
+// PROBE_MAX bucket visits: the key is then reported as not placed (-1,
+// overflow flag raised) and the column is recomputed with a larger table.
+// Tables in HBM are sized from the exact count and probe every bucket if
+// needed, so an insertion there fails only when the table is full.
+constexpr int PROBE_MAX = 32;
 typedef int32_t keys4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) keys4 lds_keys4;  // tables live in LDS
+
+// acc += x for one table value (one correctly rounded add), by the lane that
+// owns the slot in this step; the read and the write of one wave apply in
+// issue order.
+template <bool LDS>
+__device__ __forceinline__ void table_add(double *acc, double x)
+{
+    if constexpr (LDS) {
+        auto *p = (__attribute__((address_space(3))) double *)acc;
+        *p = *p + x;
+    } else {
+        *acc = *acc + x;
+    }
+}
 
 __device__ __forceinline__ int bucket_match(const keys4 kb, int32_t k)
 {
@@ -579,12 +597,15 @@ __device__ __forceinline__ keys4 load_bucket(const int32_t *key, uint32_t b)
     }
 }
 
+// `fresh` is set when this call placed k (exactly one caller per key does).
 template <bool LDS>
-__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB, int nbmask, int *ovf)
+__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB, int nbmask, int *ovf,
+                                              bool &fresh)
 {
     uint32_t b = hash_slot(k, logNB);
+    const int limit = LDS ? PROBE_MAX : nbmask + 1;
 #pragma unroll 1
-    for (int p = 0; p < PROBE_MAX; ++p) {
+    for (int p = 0; p < limit; ++p) {
         const keys4 kb = load_bucket<LDS>(key, b);
         const int hit = bucket_match(kb, k);
         if (hit >= 0) return (int)(4 * b) + hit;
@@ -594,6 +615,7 @@ __device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB
             continue;
         }
         const int old = atomicCAS(&key[4 * b + e], EMPTY_KEY, k);
+        fresh = old == EMPTY_KEY;
         if (old == EMPTY_KEY || old == k) return (int)(4 * b) + e;
         // another key took that slot: look at the same bucket again
     }
@@ -601,13 +623,40 @@ __device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB
     return -1;
 }
 
+// The same insertion split in two, so that the first-bucket reads of many
+// keys can be in flight together: home_bucket() issues the read and
+// place_key() finishes the insertion from it (a stale bucket is harmless: a
+// slot seen empty is claimed by compare-and-swap, and keys never move).
+template <bool LDS>
+__device__ __forceinline__ keys4 home_bucket(const int32_t *key, int32_t k, int logNB, uint32_t &b)
+{
+    b = hash_slot(k, logNB);
+    return load_bucket<LDS>(key, b);
+}
+
+template <bool LDS>
+__device__ __forceinline__ int place_key(int32_t *key, int32_t k, uint32_t b, keys4 kb, int logNB, int nbmask,
+                                         int *ovf, bool &fresh)
+{
+    const int hit = bucket_match(kb, k);
+    if (hit >= 0) return (int)(4 * b) + hit;
+    const int e = bucket_empty(kb);
+    if (e >= 0) {
+        const int old = atomicCAS(&key[4 * b + e], EMPTY_KEY, k);
+        fresh = old == EMPTY_KEY;
+        if (old == EMPTY_KEY || old == k) return (int)(4 * b) + e;
+    }
+    return find_or_insert<LDS>(key, k, logNB, nbmask, ovf, fresh);
+}
+
 // Lookup after all insertions (and a barrier): plain reads suffice.
 template <bool LDS>
 __device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logNB, int nbmask)
 {
     uint32_t b = hash_slot(k, logNB);
+    const int limit = LDS ? PROBE_MAX : nbmask + 1;
 #pragma unroll 1
-    for (int p = 0; p < PROBE_MAX; ++p) {
+    for (int p = 0; p < limit; ++p) {
         keys4 kb;
         if constexpr (LDS) kb = *(const lds_keys4 *)(key + 4 * b);
         else kb = *(const keys4 *)(key + 4 * b);
@@ -617,23 +666,6 @@ __device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logN
         b = (b + 1) & (uint32_t)nbmask;
     }
     return -1;
-}
-
-// Number of occupied slots (called by all NT threads; result to all).
-template <int NT, bool GS>
-__device__ int count_keys(const int32_t *tkey, int S, int *acc)
-{
-    const int tid = threadIdx.x % NT;
-    int c = 0;
-    for (int s = tid; s < S; s += NT) c += (tkey[s] != EMPTY_KEY) ? 1 : 0;
-    c = wave_sum_i(c);
-    if (tid == 0) *acc = 0;
-    group_sync<NT, GS>();
-    if (lane() == 0) atomicAdd(acc, c);
-    group_sync<NT, GS>();
-    const int m = *acc;
-    group_sync<NT, GS>();
-    return m;
 }
 
 __device__ __forceinline__ int bucket_of(int32_t k, int32_t lo, uint64_t mul, int NB)
@@ -884,7 +916,7 @@ __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t
 }
 
 // The numeric body for one column j, executed by NT threads.
-template <int NT, int MODE, int E, int D, typename IdxT, bool IS_MERGE, bool GS>
+template <int NT, int MODE, int E, int D, typename IdxT, bool IS_MERGE, bool GS, bool PIPE = false>
 __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, int cap, int NB,
                            const Scratch<IdxT> &sc)
 {
@@ -897,17 +929,27 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         tkey[s] = EMPTY_KEY;
         if (MODE != MODE_COUNT) tval[s] = 0.0;
     }
-    if (tid == 0) { sc.misc[0] = 0; sc.misc[1] = 0; }
+    if (tid == 0) { sc.misc[6] = 0; sc.misc[7] = 0; }
     group_sync<NT, GS>();
 
     // ---------------- accumulation ----------------
     // Step t of column j adds b_t * (column t of the source) to the table:
     // SpGEMM: source column = A_*k for the t-th nonzero b_kj of B_*j;
-    // merge:  source column = column j of part t, with b_t = 1 (fma(v, 1, acc)
-    //         is the correctly rounded acc + v, so parts are summed in order).
+    // merge:  source column = column j of part t, with b_t = 1 (v * 1 is
+    //         exact, so parts are summed in order).
     const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
     const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
+    // Key count and overflow: each wave counts the keys it placed.  At the
+    // end of every burst group the waves publish their counts and read all
+    // of them back; the slots alternate between two sets by group parity,
+    // so a wave that races ahead into the next group writes the other set
+    // and every wave takes the same decision (misc[6 + parity] is the
+    // probe-failure flag, ip[parity * NWV + w] the count of wave w).
+    const int w = tid / WAVE;
+    constexpr int NWV = (NT + WAVE - 1) / WAVE;
+    int keys_w = 0, m = 0, par = 0;
     bool overflow = false;
+    double sink = 0.0;  // sum of all products a lane saw (kept live, never used)
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
         // lane l of every wave holds step tb + l: row/value pointers, length, b
         const int t = tb + lane();
@@ -946,9 +988,6 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         const int32_t *dummy_r = (const int32_t *)a.dummy;
         const double *dummy_v = (const double *)a.dummy;
         int iu = 0, ioff = 0;
-        int32_t rr[D][E];
-        double vv[D][E];
-        double bb[D];
         auto issue = [&](int32_t(&r)[E], double(&v)[E], double &b) {
             const int ul = min(iu, WAVE - 1);
             const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, ul);
@@ -967,12 +1006,23 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
             ioff = more ? ioff + CH : 0;
             iu = more ? iu : iu + 1;
         };
-        // Burst groups: the loads of D consecutive chunks are issued back to
-        // back, then the chunks are folded in order (one memory latency per
-        // group; other waves and workgroups on the CU overlap it).
-        for (int g0 = 0; g0 < total && !overflow; g0 += D) {
+        // A group is D consecutive chunks: their loads are issued back to
+        // back, then the chunks are folded in order.
+        auto issue_group = [&](int32_t(&r)[D][E], double(&v)[D][E], double(&b)[D]) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) issue(rr[i], vv[i], bb[i]);
+            for (int i = 0; i < D; ++i) issue(r[i], v[i], b[i]);
+        };
+        auto fold_group = [&](int32_t(&r)[D][E], double(&v)[D][E], double(&b)[D]) {
+            // 1. place every key of the group (the order of insertions does
+            //    not matter): all first-bucket reads go out together
+            uint32_t hb[D][E];
+            keys4 kb[D][E];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    kb[i][q] = home_bucket<!GS>(tkey, max(r[i][q], 0), logS - 2, hb[i][q]);
+            int sl[D][E];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
 #pragma unroll
@@ -980,25 +1030,73 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
                     // the dummy word reads as row -1; testing the loaded
                     // row (not a separate flag) keeps the load ahead of the
                     // branch, so the compiler cannot sink it into the branch
-                    int s = -1;
-                    if (rr[i][q] >= 0 && !overflow)
-                        s = find_or_insert<!GS>(tkey, rr[i][q], logS - 2, (S >> 2) - 1, &sc.misc[1]);
-                    if (MODE != MODE_COUNT) {
-                        // unconditional update (idle lanes hit a spare word
-                        // that accumulation does not otherwise use), so the
-                        // value load is not sunk into a branch either
-                        double *dst = (s >= 0) ? tval + s : sc.p0;
-                        *dst = fma(vv[i][q], bb[i], *dst);
+                    sl[i][q] = -1;
+                    bool fresh = false;
+                    if (r[i][q] >= 0)
+                        sl[i][q] = place_key<!GS>(tkey, r[i][q], hb[i][q], kb[i][q], logS - 2, (S >> 2) - 1,
+                                                  &sc.misc[6 + par], fresh);
+                    keys_w += __popcll(ballot(fresh));
+                }
+            }
+            if (NWV > 1 && lane() == 0) sc.ip[par * NWV + w] = keys_w;
+            // 2. the value updates, chunk by chunk in order; a row may recur
+            //    in the next chunk, so chunks are separated by a barrier
+            //    (one wave: its LDS operations already apply in order)
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                if (MODE != MODE_COUNT) {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) {
+                        // every lane folds its product into `sink`, so the
+                        // value load is used outside the branch and cannot be
+                        // sunk into it (idle lanes stay out of the table)
+                        const double prod = v[i][q] * b[i];
+                        sink += prod;
+                        if (sl[i][q] >= 0) table_add<!GS>(tval + sl[i][q], prod);
                     }
                 }
-                group_sync<NT, GS>();
+                if (NWV > 1 || GS || i == D - 1) group_sync<NT, GS>();
             }
-            overflow = sc.misc[1] != 0;
+            if constexpr (NWV == 1) {
+                m = keys_w;
+            } else {
+                m = 0;
+                for (int v2 = 0; v2 < NWV; ++v2) m += sc.ip[par * NWV + v2];
+            }
+            overflow = sc.misc[6 + par] != 0 || m > cap;
+            par ^= 1;
+        };
+        int32_t rA[D][E];
+        double vA[D][E], bA[D];
+        if constexpr (!PIPE) {
+            // burst groups: one memory latency per group, overlapped only by
+            // the other waves and workgroups of the CU
+            for (int g0 = 0; g0 < total && !overflow; g0 += D) {
+                issue_group(rA, vA, bA);
+                fold_group(rA, vA, bA);
+            }
+        } else {
+            // double-buffered groups: the loads of group g+1 are in flight
+            // while group g is folded (past the last chunk the iterator
+            // issues dummy loads)
+            int32_t rB[D][E];
+            double vB[D][E], bB[D];
+            const int ng = (total + D - 1) / D;
+            issue_group(rA, vA, bA);
+            for (int g = 0; g < ng && !overflow; g += 2) {
+                issue_group(rB, vB, bB);
+                fold_group(rA, vA, bA);
+                if (g + 1 >= ng || overflow) break;
+                issue_group(rA, vA, bA);
+                fold_group(rB, vB, bB);
+            }
         }
     }
+    // products are >= 0 or NaN (dummy lanes), so this store never happens;
+    // the compiler cannot know that and keeps `sink` (and the loads) live
+    if (MODE != MODE_COUNT && sink == -1.0) sc.dmisc[3] = sink;
     group_sync<NT, GS>();
-    const int m = count_keys<NT, GS>(tkey, S, &sc.misc[0]);
-    if (sc.misc[1] || m > cap) {
+    if (overflow) {
         if (tid == 0) a.out_cnt[j] = -1;
         return;
     }
@@ -1030,6 +1128,21 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
 // ---------------------------------------------------------------------------
 // LDS-bin kernels
 // ---------------------------------------------------------------------------
+// Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals
+// workgroups round-robin over the eight dies, each with its own L2).  With
+// xcd_order set, XCD x takes the x-th contiguous eighth of the column list,
+// so neighbouring columns (which share source columns when the list is in a
+// locality order) meet in one L2.  A bijection on [0, n).
+constexpr uint32_t NUM_XCD = 8;
+
+__device__ __forceinline__ uint32_t sched_block(uint32_t b, uint32_t n, int xcd_order)
+{
+    if (!xcd_order) return b;
+    const uint32_t x = b % NUM_XCD, r = b / NUM_XCD;
+    const uint32_t q = n / NUM_XCD, rem = n % NUM_XCD;
+    return x * q + min(x, rem) + r;
+}
+
 template <int S>
 struct LdsBin {
     static constexpr int CAP = (3 * S) / 4;
@@ -1038,7 +1151,7 @@ struct LdsBin {
     using Idx = uint16_t;
 };
 
-template <int S, int NW, int CPW, int MODE, int E, int D, bool IS_MERGE>
+template <int S, int NW, int CPW, int MODE, int E, int D, bool IS_MERGE, bool PIPE>
 __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 {
     using L = LdsBin<S>;
@@ -1057,13 +1170,13 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
     };
     __shared__ Col cols[CPW] __attribute__((aligned(16)));
     const int ci = threadIdx.x / NT;
-    const int64_t idx = (int64_t)blockIdx.x * CPW + ci;
+    const int64_t idx = (int64_t)sched_block(blockIdx.x, gridDim.x, a.xcd_order) * CPW + ci;
     if (idx >= a.ncols) return;  // whole groups exit together
     Col &c = cols[ci];
     Scratch<uint16_t> sc{c.key, c.val, c.list, c.sorted, c.bcnt, c.bcur, c.p0, c.p1,
                          c.ip, c.hist, c.misc, c.dmisc, c.wsum};
     constexpr int logS = __builtin_ctz(S);
-    column_body<NT, MODE, E, D, uint16_t, IS_MERGE, false>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
+    column_body<NT, MODE, E, D, uint16_t, IS_MERGE, false, PIPE>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1108,7 +1221,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     __shared__ Sh sh __attribute__((aligned(16)));
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
-    const int64_t j = a.cols[blockIdx.x];
+    const int64_t j = a.cols[sched_block(blockIdx.x, gridDim.x, a.xcd_order)];
     int32_t *wkey = sh.key + w * SW;
     double *wval = sh.val + w * SW;
     for (int s = lane(); s < SW; s += WAVE) {
@@ -1129,6 +1242,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
     const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
     bool overflow = false;
+    int keys_w = 0;     // keys this wave placed in its slice
+    double sink = 0.0;  // sum of the products a lane saw (kept live, never used)
 
     // fold entries [c0, min(c0+64, cend)) of one source column into the slice
     auto fold = [&](const int32_t *rr, const double *vv, double b, int c0, int cend, int32_t &row0,
@@ -1138,10 +1253,12 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
         const int32_t row = ldg(in ? rr + e : dummy_r);
         double v = 0.0;
         if (MODE != MODE_COUNT) v = ldg(in ? vv + e : dummy_v);
+        bool fresh = false;
         if (in && row >= rlo && row < rhi) {
-            const int s = find_or_insert<true>(wkey, row, LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
-            if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(v, b, wval[s]);
+            const int s = find_or_insert<true>(wkey, row, LOGSW - 2, SW / 4 - 1, &sh.wovf[w], fresh);
+            if (MODE != MODE_COUNT && s >= 0) table_add<true>(wval + s, v * b);
         }
+        keys_w += __popcll(ballot(fresh));
         group_sync<WAVE>();
         row0 = readlane_i(row, 0);
         rowl = readlane_i(row, min(WAVE - 1, max(0, cend - 1 - c0)));
@@ -1266,12 +1383,15 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
                 for (int i = 0; i < D; ++i) {
                     const double b = readlane_d(bv, su[i]);
                     int s = -1;
+                    bool fresh = false;
                     if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi)
-                        s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
+                        s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w], fresh);
+                    keys_w += __popcll(ballot(fresh));
                     if (MODE != MODE_COUNT) {
-                        // idle lanes update a spare word of their wave
-                        double *dst = (s >= 0) ? wval + s : &sh.p0[w];
-                        *dst = fma(vv_[i], b, *dst);
+                        // `sink` keeps the value load out of the branch
+                        const double prod = vv_[i] * b;
+                        sink += prod;
+                        if (s >= 0) table_add<true>(wval + s, prod);
                     }
                     group_sync<WAVE>();
                     if (g0 + i < total && sic[i] == 0) frow = readlane_i(rr_[i], 0);
@@ -1281,10 +1401,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
                     const int c = g0 + i;
                     const int u = su[i], ic = sic[i];
                     const double b = readlane_d(bv, u);
+                    bool fresh = false;
                     if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
-                        const int s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w]);
-                        if (MODE != MODE_COUNT && s >= 0) wval[s] = fma(vv_[i], b, wval[s]);
+                        const int s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w],
+                                                           fresh);
+                        if (MODE != MODE_COUNT && s >= 0) table_add<true>(wval + s, vv_[i] * b);
                     }
+                    keys_w += __popcll(ballot(fresh));
                     group_sync<WAVE>();
                     if (c < total) {
                         const int wsu = readlane_i(ws, u), weu = readlane_i(we, u);
@@ -1295,19 +1418,14 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
                     }
                 }
             }
-            overflow = sh.wovf[w] != 0;
+            overflow = sh.wovf[w] != 0 || keys_w > CAPW;
         }
     }
-    {
-        // keys of this wave's slice; more than its capacity means overflow
-        int c = 0;
-        for (int q = lane(); q < SW; q += WAVE) c += (wkey[q] != EMPTY_KEY) ? 1 : 0;
-        c = wave_sum_i(c);
-        if (lane() == 0) {
-            sh.wcnt[w] = c;
-            if (c > CAPW) sh.wovf[w] = 1;
-        }
+    if (lane() == 0) {
+        sh.wcnt[w] = keys_w;
+        if (keys_w > CAPW) sh.wovf[w] = 1;
     }
+    if (MODE != MODE_COUNT && sink == -1.0) sh.dmisc[3] = sink;  // never: products are >= 0 or NaN
     __syncthreads();  // every slice is complete (LDS and the wave flags)
 
     int m = 0, off = 0, ovf = 0;
@@ -1353,8 +1471,10 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     });
 }
 
-// Launch shapes per bin: (waves per column, columns per workgroup, entries
-// per lane per chunk, chunks in flight).  Variant 0 is the default; the
+// Launch shapes per bin: (slots, waves per column, columns per workgroup,
+// entries per lane per chunk, chunks per group, double-buffered groups), or
+// the split-table kernel (waves, chunks per group).  Variant 0 is the
+// fastest shape measured on the 1M-vertex planted graph; the
 // others are alternatives the tuner may select through mcl_params.bin_policy
 // (4 bits per bin).  Merge and exact-count launches always use variant 0.
 template <int MODE, bool IS_MERGE>
@@ -1362,40 +1482,39 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 {
     const int n = a.ncols;
     if (n <= 0) return;
-#define MCL_LAUNCH(S_, NW_, CPW_, E_, D_)                                                   \
-    hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE>),              \
+#define MCL_LAUNCH(S_, NW_, CPW_, E_, D_, P_)                                               \
+    hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE, P_>),          \
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
     if (MODE == MODE_COUNT) variant = 0;
 #define MCL_SPLIT(NW_, D_)                                                                   \
     hipLaunchKernelGGL((k_numeric_split<NW_, 512, MODE, D_, IS_MERGE>), dim3(n), dim3(NW_ * WAVE), 0, \
                        st, a)
     switch (bin * 8 + variant) {
-    case 0: MCL_LAUNCH(128, 1, 4, 2, 4); break;
-    case 1: MCL_LAUNCH(128, 1, 4, 1, 8); break;
-    case 8: MCL_LAUNCH(256, 1, 4, 2, 4); break;
-    case 9: MCL_LAUNCH(256, 1, 4, 1, 8); break;
-    case 16: MCL_LAUNCH(512, 1, 4, 2, 4); break;
-    case 17: MCL_LAUNCH(512, 1, 4, 2, 8); break;
-    case 24: MCL_SPLIT(2, 4); break;
-    case 25: MCL_LAUNCH(1024, 2, 1, 2, 4); break;
-    case 26: MCL_SPLIT(2, 8); break;
-    case 27: MCL_LAUNCH(1024, 1, 2, 4, 4); break;
-    case 32: MCL_SPLIT(4, 4); break;
-    case 33: MCL_LAUNCH(2048, 4, 1, 2, 4); break;
-    case 34: MCL_SPLIT(4, 8); break;
-    case 35: MCL_LAUNCH(2048, 2, 1, 4, 4); break;
-    case 36: MCL_LAUNCH(2048, 4, 1, 2, 8); break;
-    case 40: MCL_SPLIT(8, 4); break;
-    case 41: MCL_LAUNCH(4096, 8, 1, 1, 4); break;
-    case 42: MCL_SPLIT(8, 8); break;
-    case 43: MCL_LAUNCH(4096, 4, 1, 2, 8); break;
-    case 44: MCL_LAUNCH(4096, 2, 1, 4, 8); break;
-    case 48: MCL_SPLIT(16, 4); break;
-    case 49: MCL_LAUNCH(8192, 16, 1, 1, 4); break;
-    case 50: MCL_SPLIT(16, 8); break;
-    case 51: MCL_LAUNCH(8192, 4, 1, 2, 8); break;
-    case 52: MCL_LAUNCH(8192, 2, 1, 4, 8); break;
-    case 53: MCL_LAUNCH(8192, 8, 1, 1, 8); break;
+    case 0: MCL_LAUNCH(128, 1, 4, 2, 4, false); break;
+    case 1: MCL_LAUNCH(128, 1, 4, 1, 8, false); break;
+    case 8: MCL_LAUNCH(256, 1, 4, 2, 4, false); break;
+    case 9: MCL_LAUNCH(256, 1, 4, 1, 8, false); break;
+    case 16: MCL_LAUNCH(512, 1, 4, 2, 4, false); break;
+    case 17: MCL_LAUNCH(512, 1, 4, 2, 8, false); break;
+    case 24: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
+    case 25: MCL_SPLIT(2, 4); break;
+    case 26: MCL_LAUNCH(1024, 2, 1, 2, 4, true); break;
+    case 27: MCL_LAUNCH(1024, 1, 2, 4, 4, false); break;
+    case 32: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
+    case 33: MCL_SPLIT(4, 4); break;
+    case 34: MCL_LAUNCH(2048, 4, 1, 2, 4, true); break;
+    case 35: MCL_LAUNCH(2048, 4, 1, 1, 8, true); break;
+    case 40: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
+    case 41: MCL_SPLIT(8, 4); break;
+    case 42: MCL_LAUNCH(4096, 8, 1, 1, 4, true); break;
+    case 43: MCL_LAUNCH(4096, 8, 1, 1, 8, true); break;
+    case 44: MCL_LAUNCH(4096, 8, 1, 1, 8, false); break;
+    case 48: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
+    case 49: MCL_SPLIT(16, 4); break;
+    case 50: MCL_LAUNCH(8192, 16, 1, 1, 4, true); break;
+    case 51: MCL_LAUNCH(8192, 16, 1, 1, 8, true); break;
+    case 52: MCL_LAUNCH(8192, 16, 1, 1, 8, false); break;
+    case 53: MCL_LAUNCH(8192, 16, 1, 1, 16, false); break;
     default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
     }
 #undef MCL_SPLIT
@@ -1404,7 +1523,7 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 
 int lds_bin_variants(int bin)
 {
-    static const int nv[NUM_LDS_BINS] = {2, 2, 2, 4, 5, 5, 6};
+    static const int nv[NUM_LDS_BINS] = {2, 2, 2, 4, 4, 5, 6};
     return (bin >= 0 && bin < NUM_LDS_BINS) ? nv[bin] : 1;
 }
 

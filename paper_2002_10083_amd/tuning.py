@@ -18,8 +18,9 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-VARIANTS = [2, 2, 2, 4, 5, 5, 6]        # launch variants per LDS bin
-SCALES = (1.0, 1.25, 1.5, 2.0)
+VARIANTS = [2, 2, 2, 4, 4, 5, 6]        # launch variants per LDS bin
+SCALES = (1.0, 1.25, 1.6)
+KEYS = (5, 8, 12)                       # Cohen keys per vertex
 
 
 def pack(variants) -> int:
@@ -30,37 +31,38 @@ def unpack(policy: int):
     return [(policy >> (4 * b)) & 15 for b in range(len(VARIANTS))]
 
 
-def load_policy(key: str, default=(0, 1.0)):
+def load_policy(key: str, default=(0, 1.0, 5)):
+    """(bin_policy, est_scale, cohen_keys) stored for `key`, else `default`."""
     try:
         with open(TUNED) as f:
             d = json.load(f)
         e = d[key]
-        return int(e["bin_policy"], 0), float(e["est_scale"])
+        return int(e["bin_policy"], 0), float(e["est_scale"]), int(e.get("cohen_keys", default[2]))
     except (OSError, KeyError, ValueError):
         return default
 
 
-def save_policy(key: str, policy: int, scale: float, info: dict):
+def save_policy(key: str, policy: int, scale: float, keys: int, info: dict, path: str = TUNED):
     d = {}
-    if os.path.exists(TUNED):
-        with open(TUNED) as f:
+    if os.path.exists(path):
+        with open(path) as f:
             d = json.load(f)
-    d[key] = dict(bin_policy=hex(policy), est_scale=scale, **info)
-    with open(TUNED, "w") as f:
+    d[key] = dict(bin_policy=hex(policy), est_scale=scale, cohen_keys=keys, **info)
+    with open(path, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
 
 
 def tune(run, reps=2, log=print):
-    """run(policy, scale) -> stats dict of one step (bin_ms, t_total_ms).
-    Returns (policy, scale, report)."""
+    """run(policy, scale, keys) -> stats dict of one step (bin_ms, t_total_ms).
+    Returns (policy, scale, keys, report)."""
     import torch
 
-    def measure(policy, scale):
+    def measure(policy, scale, keys=5):
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
             t = time.perf_counter()
-            st = run(policy, scale)
+            st = run(policy, scale, keys)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t) * 1e3
             if best is None or dt < best[0]:
@@ -84,11 +86,12 @@ def tune(run, reps=2, log=print):
         variants[b] = min(range(len(times)), key=lambda v: times[v])
         report["bins"][b] = [round(t, 3) for t in times]
         log("bin %d variant times %s -> %d" % (b, report["bins"][b], variants[b]))
-    best_scale, best_ms = scale, None
-    for sc in SCALES:
-        ms, st = measure(pack(variants), sc)
-        log("scale %.2f: %.1f ms (overflow %d)" % (sc, ms, st["n_overflow"]))
-        if best_ms is None or ms < best_ms:
-            best_scale, best_ms = sc, ms
+    best_scale, best_keys, best_ms = scale, 5, None
+    for r in KEYS:
+        for sc in SCALES:
+            ms, st = measure(pack(variants), sc, r)
+            log("keys %d scale %.2f: %.1f ms (overflow %d)" % (r, sc, ms, st["n_overflow"]))
+            if best_ms is None or ms < best_ms:
+                best_scale, best_keys, best_ms = sc, r, ms
     report["final_ms"] = best_ms
-    return pack(variants), best_scale, report
+    return pack(variants), best_scale, best_keys, report

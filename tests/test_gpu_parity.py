@@ -12,6 +12,7 @@ from mclgen import (CSC, clique_union, config0_graph, planted_graph, random_csc,
                     random_symmetric_graph, planted_components)
 from gpu_helpers import (csc_columns_equal, max_rel_diff_on_equal_columns, restrict_columns,
                          tie_explains)
+from paper_2002_10083_amd.tuning import VARIANTS as _NV
 
 pytestmark = pytest.mark.gpu
 
@@ -172,7 +173,9 @@ def test_iterate_parity_small_k(mcl, S, R, theta):
     check_iterate(mcl, A, theta=theta, S=S, R=R)
 
 
-ALL_VARIANTS = [0x0, 0x1111111, 0x2222222, 0x2222010]
+# policy v uses variant min(v, count - 1) in every bin: together they cover
+# every launch shape of every bin
+ALL_VARIANTS = [sum(min(v, nv - 1) << (4 * b) for b, nv in enumerate(_NV)) for v in range(max(_NV))]
 
 
 def test_launch_variants_are_bit_identical(mcl):
