@@ -314,6 +314,22 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         HIPC(hipMemsetAsync(dummy, 0xFF, 8 * sizeof(int64_t), mem.st));  // row -1 (no row)
         a.dummy = dummy;
     }
+    // sliced copy of the source matrix when a sliced-table launch is chosen
+    // (every other launch accepts it too: entries of a step stay distinct)
+    if (!a.parts) {
+        bool sliced = false;
+        for (int b = 3; b <= 6; ++b) sliced |= mcl::lds_variant_sliced(b, (int)((policy >> (4 * b)) & 15u));
+        if (sliced && a.A.ncols > 0) {
+            const int64_t nz = std::max<int64_t>(a.A.nnz, 1);
+            int32_t *ro = mem.ws<int32_t>(nz);
+            double *vo = mem.ws<double>(nz);
+            int32_t *go = mem.ws<int32_t>(a.A.ncols * 17);
+            mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
+            a.A.rowidx = ro;
+            a.A.val = vo;
+            a.goff = go;
+        }
+    }
     a.lo = pl.lo;
     a.hi = pl.hi;
     a.out_base = pl.base;

@@ -43,12 +43,16 @@ struct NumericArgs {
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     int32_t xcd_order;        // nonzero: contiguous runs of the column list per XCD
+    const int32_t *goff;      // sliced layout of A: 17 group boundaries per column (or null)
 };
 
 // ---- spgemm.hip
 constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin
+bool lds_variant_sliced(int bin, int variant);       // launch reads the sliced layout of A
+// sliced copy of A (entries of each column ordered by row group) + boundaries
+void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
 void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
                      const float *ckeys, int r, float *est, float *feat, const int64_t *prev_nnz,
                      int iteration, hipStream_t st);

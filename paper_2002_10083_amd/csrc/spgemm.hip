@@ -597,12 +597,11 @@ __device__ __forceinline__ keys4 load_bucket(const int32_t *key, uint32_t b)
     }
 }
 
-// `fresh` is set when this call placed k (exactly one caller per key does).
+// Insert k starting at bucket b.  `fresh` is set when this call placed k
+// (exactly one caller per key does).
 template <bool LDS>
-__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB, int nbmask, int *ovf,
-                                              bool &fresh)
+__device__ __forceinline__ int insert_from(int32_t *key, int32_t k, uint32_t b, int nbmask, int *ovf, bool &fresh)
 {
-    uint32_t b = hash_slot(k, logNB);
     const int limit = LDS ? PROBE_MAX : nbmask + 1;
 #pragma unroll 1
     for (int p = 0; p < limit; ++p) {
@@ -623,20 +622,21 @@ __device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB
     return -1;
 }
 
-// The same insertion split in two, so that the first-bucket reads of many
-// keys can be in flight together: home_bucket() issues the read and
-// place_key() finishes the insertion from it (a stale bucket is harmless: a
-// slot seen empty is claimed by compare-and-swap, and keys never move).
 template <bool LDS>
-__device__ __forceinline__ keys4 home_bucket(const int32_t *key, int32_t k, int logNB, uint32_t &b)
+__device__ __forceinline__ int find_or_insert(int32_t *key, int32_t k, int logNB, int nbmask, int *ovf,
+                                              bool &fresh)
 {
-    b = hash_slot(k, logNB);
-    return load_bucket<LDS>(key, b);
+    return insert_from<LDS>(key, k, hash_slot(k, logNB), nbmask, ovf, fresh);
 }
 
+// The same insertion split in two, so that the first-bucket reads of many
+// keys can be in flight together: the caller reads the home bucket b of k
+// (load_bucket) and place_key() finishes the insertion from it (a stale
+// bucket is harmless: a slot seen empty is claimed by compare-and-swap, and
+// keys never move).
 template <bool LDS>
-__device__ __forceinline__ int place_key(int32_t *key, int32_t k, uint32_t b, keys4 kb, int logNB, int nbmask,
-                                         int *ovf, bool &fresh)
+__device__ __forceinline__ int place_key(int32_t *key, int32_t k, uint32_t b, keys4 kb, int nbmask, int *ovf,
+                                         bool &fresh)
 {
     const int hit = bucket_match(kb, k);
     if (hit >= 0) return (int)(4 * b) + hit;
@@ -646,14 +646,13 @@ __device__ __forceinline__ int place_key(int32_t *key, int32_t k, uint32_t b, ke
         fresh = old == EMPTY_KEY;
         if (old == EMPTY_KEY || old == k) return (int)(4 * b) + e;
     }
-    return find_or_insert<LDS>(key, k, logNB, nbmask, ovf, fresh);
+    return insert_from<LDS>(key, k, b, nbmask, ovf, fresh);
 }
 
 // Lookup after all insertions (and a barrier): plain reads suffice.
 template <bool LDS>
-__device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logNB, int nbmask)
+__device__ __forceinline__ int find_from(const int32_t *key, int32_t k, uint32_t b, int nbmask)
 {
-    uint32_t b = hash_slot(k, logNB);
     const int limit = LDS ? PROBE_MAX : nbmask + 1;
 #pragma unroll 1
     for (int p = 0; p < limit; ++p) {
@@ -666,6 +665,12 @@ __device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logN
         b = (b + 1) & (uint32_t)nbmask;
     }
     return -1;
+}
+
+template <bool LDS>
+__device__ __forceinline__ int find_slot(const int32_t *key, int32_t k, int logNB, int nbmask)
+{
+    return find_from<LDS>(key, k, hash_slot(k, logNB), nbmask);
 }
 
 __device__ __forceinline__ int bucket_of(int32_t k, int32_t lo, uint64_t mul, int NB)
@@ -1021,7 +1026,10 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
             for (int i = 0; i < D; ++i)
 #pragma unroll
                 for (int q = 0; q < E; ++q)
-                    kb[i][q] = home_bucket<!GS>(tkey, max(r[i][q], 0), logS - 2, hb[i][q]);
+                {
+                    hb[i][q] = hash_slot(max(r[i][q], 0), logS - 2);
+                    kb[i][q] = load_bucket<!GS>(tkey, hb[i][q]);
+                }
             int sl[D][E];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
@@ -1033,7 +1041,7 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
                     sl[i][q] = -1;
                     bool fresh = false;
                     if (r[i][q] >= 0)
-                        sl[i][q] = place_key<!GS>(tkey, r[i][q], hb[i][q], kb[i][q], logS - 2, (S >> 2) - 1,
+                        sl[i][q] = place_key<!GS>(tkey, r[i][q], hb[i][q], kb[i][q], (S >> 2) - 1,
                                                   &sc.misc[6 + par], fresh);
                     keys_w += __popcll(ballot(fresh));
                 }
@@ -1180,37 +1188,97 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Split-table kernel for large columns: NW waves per column, wave w owning
-// the rows of one slice [rlo_w, rhi_w) of the column's row span and a private
-// table of SW slots.  A_*k has ascending rows, so each wave fetches only the
-// slice of every A_*k that can hold its rows: the window comes from linear
-// interpolation between the first and last row of A_*k, widened by SLACK
-// entries and then verified (the entries just outside the window must lie
-// outside the slice; otherwise the window is extended).  Waves never touch
-// each other's rows, so accumulation needs no barrier, each wave keeps
-// ascending-k order for its rows, and a wave skips every A_*k whose row range
-// misses its slice.  The column's sorted order is the concatenation of the
-// waves' sorted slices.
+// Sliced source layout and the sliced-table kernel for large columns.
+//
+// Rows are dealt to NG = 16 groups by the top four bits of their
+// multiplicative hash.  The sliced copy of a source matrix keeps every column
+// in place but orders its entries by group (rows ascending inside a group)
+// and records the 17 group boundaries of the column.  A workgroup of NW
+// waves then gives wave w the groups [w*G, (w+1)*G), G = NG/NW, with a
+// private table of SW slots: the entries of A_*k that wave w needs are one
+// contiguous, exactly known run, waves never share a row, so accumulation
+// needs no barrier, and a wave's LDS operations apply in issue order, which
+// keeps the ascending-k order of every row.  Hashed groups spread the rows
+// of a column evenly over the waves whatever the vertex numbering.
 // ---------------------------------------------------------------------------
-constexpr int SPLIT_SLACK = 16;
+constexpr int NG = 16;
 
-template <int NW, int SW, int MODE, int D, bool IS_MERGE>
-__global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
+__device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * 2654435761u; }
+__device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >> 28); }
+// home bucket inside a sub-table of 2^logNB buckets: the hash bits below the group bits
+__device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return (row_hash(r) << 4) >> (32 - logNB); }
+
+// One wave per column: group sizes, boundaries, then a stable scatter.
+__global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restrict__ rowo,
+                                                      double *__restrict__ valo, int32_t *__restrict__ goff)
+{
+    const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
+    if (k >= A.ncols) return;
+    const int64_t p0 = A.colptr[k];
+    const int len = (int)(A.colptr[k + 1] - p0);
+    int cnt = 0;  // lane g < NG: size of group g
+    for (int c = 0; c < len; c += WAVE) {
+        const int e = c + lane();
+        const int g = (e < len) ? row_group(A.rowidx[p0 + e]) : NG;
+        for (int q = 0; q < NG; ++q) {
+            const int n = __popcll(ballot(g == q));
+            if (lane() == q) cnt += n;
+        }
+    }
+    const int own = (lane() < NG) ? cnt : 0;
+    int cur = wave_incl_scan(own) - own;  // lane g: first position of group g; lane NG: len
+    if (lane() <= NG) goff[k * (NG + 1) + lane()] = cur;
+    for (int c = 0; c < len; c += WAVE) {
+        const int e = c + lane();
+        const bool in = e < len;
+        const int32_t r = in ? A.rowidx[p0 + e] : 0;
+        const double v = in ? A.val[p0 + e] : 0.0;
+        const int g = in ? row_group(r) : NG;
+        uint64_t mine = 0;
+        int base = 0;
+        for (int q = 0; q < NG; ++q) {
+            const uint64_t bq = ballot(g == q);
+            const int cq = readlane_i(cur, q);
+            if (g == q) {
+                mine = bq;
+                base = cq;
+            }
+            if (lane() == q) cur += __popcll(bq);
+        }
+        if (in) {
+            const int64_t d = p0 + base + popc_below(mine);
+            rowo[d] = r;
+            valo[d] = v;
+        }
+    }
+}
+
+void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st)
+{
+    if (A.ncols <= 0) return;
+    hipLaunchKernelGGL(k_slice_layout, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A, rowo, valo,
+                       goff);
+}
+
+template <int NW, int SW, int MODE, int D>
+__global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
 {
     constexpr int NT = NW * WAVE;
-    constexpr int CAPW = (3 * SW) / 4;
-    constexpr int NBW = (SW / 4 < 64) ? 64 : SW / 4;
+    constexpr int G = NG / NW;                 // groups per wave
+    constexpr int CAPW = (13 * SW) / 16;       // keys per wave table
+    constexpr int NBW = SW / 4;                // buckets per wave table
+    constexpr int LOGNBW = __builtin_ctz(NBW);
     constexpr int STOT = NW * SW;
     constexpr int CAPT = NW * CAPW;
+    constexpr int NBS = STOT / 4;              // sort buckets
     constexpr int NBLK = CAPT / WAVE + 2;
-    constexpr int LOGSW = __builtin_ctz(SW);
-    static_assert(STOT <= 65536, "slot ids are 16-bit");
+    static_assert(NG % NW == 0 && STOT <= 65536, "layout");
     struct alignas(16) Sh {
         double val[STOT];
         int32_t key[STOT];
         double p0[NBLK], p1[NBLK];
         int32_t ip[NBLK];
-        int32_t bcnt[NW * NBW], bcur[NW * NBW];
+        int32_t bcnt[NBS], bcur[NBS];
         int32_t hist[256];
         uint16_t list[CAPT], sorted[CAPT];
         int32_t wcnt[NW], wovf[NW];
@@ -1221,203 +1289,81 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
     __shared__ Sh sh __attribute__((aligned(16)));
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
-    const int64_t j = a.cols[sched_block(blockIdx.x, gridDim.x, a.xcd_order)];
+    const int64_t j = a.cols[blockIdx.x];
     int32_t *wkey = sh.key + w * SW;
     double *wval = sh.val + w * SW;
     for (int s = lane(); s < SW; s += WAVE) {
         wkey[s] = EMPTY_KEY;
         if (MODE != MODE_COUNT) wval[s] = 0.0;
     }
-    if (lane() == 0) { sh.wcnt[w] = 0; sh.wovf[w] = 0; }
+    if (lane() == 0) sh.wovf[w] = 0;
     group_sync<WAVE>();
 
-    const int32_t lo = a.lo[j];
-    const int64_t span = (int64_t)a.hi[j] - lo + 1;
-    // owner(row) = floor((row - lo) * NW / span); slice w = [rlo, rhi)
-    const int32_t rlo = lo + (int32_t)(((int64_t)w * span + NW - 1) / NW);
-    const int32_t rhi = lo + (int32_t)(((int64_t)(w + 1) * span + NW - 1) / NW);
     const int32_t *dummy_r = (const int32_t *)a.dummy;
     const double *dummy_v = (const double *)a.dummy;
-
-    const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
-    const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
+    const int64_t bs = a.B.colptr[j];
+    const int mj = (int)(a.B.colptr[j + 1] - bs);
     bool overflow = false;
-    int keys_w = 0;     // keys this wave placed in its slice
+    int keys_w = 0;     // keys this wave placed
     double sink = 0.0;  // sum of the products a lane saw (kept live, never used)
 
-    // fold entries [c0, min(c0+64, cend)) of one source column into the slice
-    auto fold = [&](const int32_t *rr, const double *vv, double b, int c0, int cend, int32_t &row0,
-                    int32_t &rowl) {
-        const int e = c0 + lane();
-        const bool in = e < cend;
-        const int32_t row = ldg(in ? rr + e : dummy_r);
-        double v = 0.0;
-        if (MODE != MODE_COUNT) v = ldg(in ? vv + e : dummy_v);
-        bool fresh = false;
-        if (in && row >= rlo && row < rhi) {
-            const int s = find_or_insert<true>(wkey, row, LOGSW - 2, SW / 4 - 1, &sh.wovf[w], fresh);
-            if (MODE != MODE_COUNT && s >= 0) table_add<true>(wval + s, v * b);
-        }
-        keys_w += __popcll(ballot(fresh));
-        group_sync<WAVE>();
-        row0 = readlane_i(row, 0);
-        rowl = readlane_i(row, min(WAVE - 1, max(0, cend - 1 - c0)));
-    };
-
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
-        // lane l describes step tb + l: source column pointers, length, b,
-        // first/last row, and this wave's window [ws, we) in it
+        // lane l: step tb + l -- start and length of this wave's run in A_*k, b
         const int t = tb + lane();
-        const int32_t *rp = nullptr;
-        const double *vp = nullptr;
-        int klen = 0;
-        double bv = 1.0;
+        int64_t ws = 0;
+        int len = 0;
+        double bv = 0.0;
         if (t < mj) {
-            if constexpr (IS_MERGE) {
-                const DevCSC &P = a.parts[t];
-                const int64_t p0 = P.colptr[j];
-                rp = P.rowidx + p0;
-                vp = P.val + p0;
-                klen = (int)(P.colptr[j + 1] - p0);
-            } else {
-                const int k = a.B.rowidx[bs + t];
-                bv = a.B.val[bs + t];
-                const int64_t p0 = a.A.colptr[k];
-                rp = a.A.rowidx + p0;
-                vp = a.A.val + p0;
-                klen = (int)(a.A.colptr[k + 1] - p0);
-            }
+            const int k = a.B.rowidx[bs + t];
+            bv = a.B.val[bs + t];
+            const int32_t *go = a.goff + (int64_t)k * (NG + 1);
+            const int g0 = go[w * G], g1 = go[(w + 1) * G];
+            ws = a.A.colptr[k] + g0;
+            len = g1 - g0;
         }
-        int ws = 0, we = 0;
-        if (klen > 0) {
-            const int32_t fr = ldg(rp), lr = ldg(rp + klen - 1);
-            if (!(rhi <= fr || rlo > lr)) {
-                const float sc = (float)klen / (float)((int64_t)lr - fr + 1);
-                const int g0 = (rlo <= fr) ? 0 : (int)((float)(rlo - fr) * sc);
-                const int g1 = (rhi > lr) ? klen : (int)((float)(rhi - fr) * sc);
-                ws = (rlo <= fr) ? 0 : max(0, g0 - SPLIT_SLACK);
-                we = (rhi > lr) ? klen : min(klen, g1 + SPLIT_SLACK);
-                if (we <= ws) { ws = max(0, min(ws, klen - 1)); we = ws + 1; }
-            }
-        }
-        const int nch = (we - ws + WAVE - 1) / WAVE;        // chunks of this step's window
-        const int cpre = wave_incl_scan(nch) - nch;          // chunks before this step
+        const int nch = (len + WAVE - 1) / WAVE;
+        const int cpre = wave_incl_scan(nch) - nch;
         const int total = readlane_i(cpre + nch, WAVE - 1);
-        // chunk c of the batch -> (step, chunk within the step's window)
-        auto locate = [&](int c, int &u, int &ic) {
-            const uint64_t m = ballot(nch > 0 && cpre <= c);
-            u = (m != 0) ? 63 - __clzll(m) : 0;
-            ic = c - readlane_i(cpre, u);
-        };
-        int32_t frow = 0;
-        // After the last chunk of step u: verify its window and extend it
-        // while rows of the slice may lie outside (entries of one step have
-        // distinct rows, so their order does not matter).
-        auto extend = [&](int u, int ic, int wsu, int weu, double b, int32_t lrow) {
-            (void)ic;
-            const int L = readlane_i(klen, u);
-            const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, u);
-            const double *vb = (const double *)readlane_i64((int64_t)vp, u);
-            int cws = wsu, cwe = weu;
-            int32_t r0 = frow, rl = lrow;
-            while (cws > 0 && r0 >= rlo) {
-                const int n0 = max(0, cws - WAVE);
-                int32_t x0, xl;
-                fold(rb, vb, b, n0, cws, x0, xl);
-                r0 = x0;
-                cws = n0;
-            }
-            while (cwe < L && rl < rhi) {
-                const int n1 = min(L, cwe + WAVE);
-                int32_t x0, xl;
-                fold(rb, vb, b, cwe, n1, x0, xl);
-                rl = xl;
-                cwe = n1;
-            }
-        };
-        // Burst groups: the loads of D consecutive chunks are issued back to
-        // back, then the chunks are folded in order.  One memory latency is
-        // paid per group; the other waves of the CU overlap it.
-        const int32_t *dmy_r = dummy_r;
-        for (int g0 = 0; g0 < total && !overflow; g0 += D) {
-            int32_t rr_[D];
-            double vv_[D];
-            bool in_[D];
-            int su[D], sic[D];
+        // Burst groups of D chunks: loads issued back to back, first-bucket
+        // reads of all D chunks together, then insertion and the value
+        // updates chunk by chunk (in issue order).
+        for (int c0 = 0; c0 < total && !overflow; c0 += D) {
+            int32_t rr[D];
+            double vv[D], bb[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const int c = g0 + i;
-                locate(c, su[i], sic[i]);
-                const int u = su[i];
-                const int32_t *rb = (const int32_t *)readlane_i64((int64_t)rp, u);
-                const double *vb = (const double *)readlane_i64((int64_t)vp, u);
-                const int c0 = readlane_i(ws, u) + sic[i] * WAVE;
-                const int ce = readlane_i(we, u);
-                const int e = c0 + lane();
-                in_[i] = (c < total) && e < ce;
-                rr_[i] = ldg(in_[i] ? rb + e : dmy_r);
-                if (MODE != MODE_COUNT) vv_[i] = ldg(in_[i] ? vb + e : dummy_v);
+                const int c = c0 + i;
+                const uint64_t mk = ballot(nch > 0 && cpre <= c);
+                const int u = (mk != 0) ? 63 - __clzll(mk) : 0;
+                const int ic = c - readlane_i(cpre, u);
+                const int64_t base = readlane_i64(ws, u) + (int64_t)ic * WAVE;
+                const int e = ic * WAVE + lane();
+                const bool in = (c < total) && e < readlane_i(len, u);
+                rr[i] = ldg(in ? a.A.rowidx + base + lane() : dummy_r);
+                if (MODE != MODE_COUNT) vv[i] = ldg(in ? a.A.val + base + lane() : dummy_v);
+                bb[i] = readlane_d(bv, u);
             }
-            // Does any window completed in this group need an extension?
-            // (register-only check; the common answer is no, and then the
-            // group is folded by a straight-line path without extra loads)
-            bool any_ext = false;
-            {
-                int32_t fr_c = frow;
+            uint32_t hb[D];
+            keys4 kb[D];
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const int c = g0 + i;
-                    const int u = su[i], ic = sic[i];
-                    if (c < total) {
-                        const int wsu = readlane_i(ws, u), weu = readlane_i(we, u);
-                        if (ic == 0) fr_c = readlane_i(rr_[i], 0);
-                        if (ic == readlane_i(nch, u) - 1) {
-                            const int32_t lr_c = readlane_i(rr_[i], min(WAVE - 1, weu - 1 - (wsu + ic * WAVE)));
-                            any_ext |= (wsu > 0 && fr_c >= rlo) || (weu < readlane_i(klen, u) && lr_c < rhi);
-                        }
-                    }
-                }
+            for (int i = 0; i < D; ++i) {
+                hb[i] = sub_bucket(max(rr[i], 0), LOGNBW);
+                kb[i] = load_bucket<true>(wkey, hb[i]);
             }
-            if (!any_ext) {
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const double b = readlane_d(bv, su[i]);
-                    int s = -1;
-                    bool fresh = false;
-                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi)
-                        s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w], fresh);
-                    keys_w += __popcll(ballot(fresh));
-                    if (MODE != MODE_COUNT) {
-                        // `sink` keeps the value load out of the branch
-                        const double prod = vv_[i] * b;
-                        sink += prod;
-                        if (s >= 0) table_add<true>(wval + s, prod);
-                    }
-                    group_sync<WAVE>();
-                    if (g0 + i < total && sic[i] == 0) frow = readlane_i(rr_[i], 0);
-                }
-            } else {
-                for (int i = 0; i < D; ++i) {
-                    const int c = g0 + i;
-                    const int u = su[i], ic = sic[i];
-                    const double b = readlane_d(bv, u);
-                    bool fresh = false;
-                    if (in_[i] && rr_[i] >= rlo && rr_[i] < rhi) {
-                        const int s = find_or_insert<true>(wkey, rr_[i], LOGSW - 2, SW / 4 - 1, &sh.wovf[w],
-                                                           fresh);
-                        if (MODE != MODE_COUNT && s >= 0) table_add<true>(wval + s, vv_[i] * b);
-                    }
-                    keys_w += __popcll(ballot(fresh));
-                    group_sync<WAVE>();
-                    if (c < total) {
-                        const int wsu = readlane_i(ws, u), weu = readlane_i(we, u);
-                        if (ic == 0) frow = readlane_i(rr_[i], 0);
-                        if (ic == readlane_i(nch, u) - 1)
-                            extend(u, ic, wsu, weu, b,
-                                   readlane_i(rr_[i], min(WAVE - 1, weu - 1 - (wsu + ic * WAVE))));
-                    }
+            for (int i = 0; i < D; ++i) {
+                int sl = -1;
+                bool fresh = false;
+                if (rr[i] >= 0) sl = place_key<true>(wkey, rr[i], hb[i], kb[i], NBW - 1, &sh.wovf[w], fresh);
+                keys_w += __popcll(ballot(fresh));
+                if (MODE != MODE_COUNT) {
+                    // `sink` keeps the value load out of the branch
+                    const double prod = vv[i] * bb[i];
+                    sink += prod;
+                    if (sl >= 0) table_add<true>(wval + sl, prod);
                 }
             }
+            group_sync<WAVE>();
             overflow = sh.wovf[w] != 0 || keys_w > CAPW;
         }
     }
@@ -1426,15 +1372,14 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
         if (keys_w > CAPW) sh.wovf[w] = 1;
     }
     if (MODE != MODE_COUNT && sink == -1.0) sh.dmisc[3] = sink;  // never: products are >= 0 or NaN
-    __syncthreads();  // every slice is complete (LDS and the wave flags)
+    __syncthreads();
 
-    int m = 0, off = 0, ovf = 0;
+    int m = 0, ovf = 0;
     for (int q = 0; q < NW; ++q) {
-        const int c = sh.wcnt[q];
-        if (q < w) off += c;
-        m += c;
+        m += sh.wcnt[q];
         ovf |= sh.wovf[q];
     }
+    if (a.capv && m > a.capv[j]) ovf = 1;  // more keys than the column's output slot holds
     if (ovf) {
         if (tid == 0) a.out_cnt[j] = -1;
         return;
@@ -1443,37 +1388,34 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_split(NumericArgs a)
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
+    const int32_t lo = a.lo[j];
+    const int64_t span = (int64_t)a.hi[j] - lo + 1;
     const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
-    const int mw = sh.wcnt[w];
-    uint16_t *wlist = sh.list + w * CAPW;
     if (MODE == MODE_EXPAND) {
-        sort_table<WAVE, false, uint16_t>(wkey, SW, mw, rlo, (int64_t)rhi - rlo, sh.bcnt + w * NBW,
-                                          sh.bcur + w * NBW, NBW, wlist, &sh.wsum[w],
-                                          [&](int rank, int s) {
-                                              a.out_row[base + off + rank] = wkey[s];
-                                              a.out_val[base + off + rank] = wval[s];
-                                          });
+        sort_table<NT, false, uint16_t>(sh.key, STOT, m, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
+                                        [&](int rank, int s) {
+                                            a.out_row[base + rank] = sh.key[s];
+                                            a.out_val[base + rank] = sh.val[s];
+                                        });
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
-    sort_table<WAVE, false, uint16_t>(wkey, SW, mw, rlo, (int64_t)rhi - rlo, sh.bcnt + w * NBW,
-                                      sh.bcur + w * NBW, NBW, wlist, &sh.wsum[w],
-                                      [&](int rank, int s) { sh.sorted[off + rank] = (uint16_t)(w * SW + s); });
+    sort_table<NT, false, uint16_t>(sh.key, STOT, m, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
+                                    [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
     __syncthreads();
     Scratch<uint16_t> sc{sh.key, sh.val, sh.list, sh.sorted, sh.bcnt, sh.bcur, sh.p0, sh.p1,
                          sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
-    const int32_t hi = a.hi[j];
     iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, sh.key, sh.val, sc, [&](int32_t k) {
-        if (k < lo || k > hi) return -1;
-        const int ow = (int)(((int64_t)(k - lo) * NW) / span);
-        const int s = find_slot<true>(sh.key + ow * SW, k, LOGSW - 2, SW / 4 - 1);
+        const int ow = row_group(k) / G;
+        const int s = find_from<true>(sh.key + ow * SW, k, sub_bucket(k, LOGNBW), NBW - 1);
         return (s < 0) ? -1 : ow * SW + s;
     });
 }
 
 // Launch shapes per bin: (slots, waves per column, columns per workgroup,
 // entries per lane per chunk, chunks per group, double-buffered groups), or
-// the split-table kernel (waves, chunks per group).  Variant 0 is the
+// the sliced-table kernel (waves, chunks per group; variant 1 of bins 3-6,
+// which needs the sliced source layout).  Variant 0 is the
 // fastest shape measured on the 1M-vertex planted graph; the
 // others are alternatives the tuner may select through mcl_params.bin_policy
 // (4 bits per bin).  Merge and exact-count launches always use variant 0.
@@ -1487,8 +1429,8 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
     if (MODE == MODE_COUNT) variant = 0;
 #define MCL_SPLIT(NW_, D_)                                                                   \
-    hipLaunchKernelGGL((k_numeric_split<NW_, 512, MODE, D_, IS_MERGE>), dim3(n), dim3(NW_ * WAVE), 0, \
-                       st, a)
+    if constexpr (!IS_MERGE && MODE != MODE_COUNT)                                           \
+        hipLaunchKernelGGL((k_numeric_hsplit<NW_, 512, MODE, D_>), dim3(n), dim3(NW_ * WAVE), 0, st, a)
     switch (bin * 8 + variant) {
     case 0: MCL_LAUNCH(128, 1, 4, 2, 4, false); break;
     case 1: MCL_LAUNCH(128, 1, 4, 1, 8, false); break;
@@ -1497,20 +1439,20 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 16: MCL_LAUNCH(512, 1, 4, 2, 4, false); break;
     case 17: MCL_LAUNCH(512, 1, 4, 2, 8, false); break;
     case 24: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
-    case 25: MCL_SPLIT(2, 4); break;
+    case 25: MCL_SPLIT(2, 8); break;
     case 26: MCL_LAUNCH(1024, 2, 1, 2, 4, true); break;
     case 27: MCL_LAUNCH(1024, 1, 2, 4, 4, false); break;
     case 32: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
-    case 33: MCL_SPLIT(4, 4); break;
+    case 33: MCL_SPLIT(4, 8); break;
     case 34: MCL_LAUNCH(2048, 4, 1, 2, 4, true); break;
     case 35: MCL_LAUNCH(2048, 4, 1, 1, 8, true); break;
     case 40: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
-    case 41: MCL_SPLIT(8, 4); break;
+    case 41: MCL_SPLIT(8, 8); break;
     case 42: MCL_LAUNCH(4096, 8, 1, 1, 4, true); break;
     case 43: MCL_LAUNCH(4096, 8, 1, 1, 8, true); break;
     case 44: MCL_LAUNCH(4096, 8, 1, 1, 8, false); break;
     case 48: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
-    case 49: MCL_SPLIT(16, 4); break;
+    case 49: MCL_SPLIT(16, 8); break;
     case 50: MCL_LAUNCH(8192, 16, 1, 1, 4, true); break;
     case 51: MCL_LAUNCH(8192, 16, 1, 1, 8, true); break;
     case 52: MCL_LAUNCH(8192, 16, 1, 1, 8, false); break;
@@ -1520,6 +1462,8 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 #undef MCL_SPLIT
 #undef MCL_LAUNCH
 }
+
+bool lds_variant_sliced(int bin, int variant) { return bin >= 3 && bin <= 6 && variant == 1; }
 
 int lds_bin_variants(int bin)
 {
