@@ -89,6 +89,160 @@ def cpu_baseline(W, target_s=12.0, seed=7):
                       % (k, n, seed, dt, fl, nz / dt)}
 
 
+def _line(metric, value, unit, ms, higher, workload, extra, steps=1, warmup=0, dtype="f64"):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": round(ms, 3), "higher_is_better": higher, "scaling": "strong", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic", "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+def bench_merge(args):
+    """Section 5 / Alg. 2: the inner dimension of A*A (1M-vertex planted graph)
+    cut into 8 SUMMA stages; partial products merged by the binary schedule
+    vs all at once."""
+    import torch
+    from mclgen import config1_graph
+    from paper_2002_10083_amd import drivers, mcl, tuning
+    W = config1_graph(n=args.n, n_clusters=max(1, args.n // 20))
+    A = mcl.DeviceCSC.from_host(W)
+    mcl.normalize_(A)
+    policy, scale, keys = tuning.load_policy("iterate")
+    params = mcl.default_params(bin_policy=policy, est_scale=scale, cohen_keys=keys)
+    res = {}
+    for sched in ("binary", "flat", "binary"):       # first run warms up
+        torch.cuda.reset_peak_memory_stats()
+        C, info = drivers.summa_merge(A, 8, sched, params)
+        info["torch_peak_bytes"] = torch.cuda.max_memory_allocated()
+        res[sched] = info
+        del C
+        torch.cuda.empty_cache()
+    b, f = res["binary"], res["flat"]
+    tot_b = b["t_expand_ms"] + b["t_merge_ms"]
+    tot_f = f["t_expand_ms"] + f["t_merge_ms"]
+    merged_in = sum(b["partial_nnz"])
+    return _line("merge throughput of the binary (Alg. 2) schedule: partial-product nnz merged per s",
+                 round(merged_in / (b["t_merge_ms"] * 1e-3), 1), "nnz/s", tot_b, True,
+                 "8 SUMMA stages of A*A on the 1M-vertex planted graph (seed 1001); partials merged "
+                 "by Alg. 2 vs one 8-way merge",
+                 {"binary": {k: b[k] for k in ("t_expand_ms", "t_merge_ms", "peak_list_bytes",
+                                               "torch_peak_bytes", "merges", "nnz")},
+                  "flat": {k: f[k] for k in ("t_expand_ms", "t_merge_ms", "peak_list_bytes",
+                                             "torch_peak_bytes", "merges", "nnz")},
+                  "partial_nnz": b["partial_nnz"],
+                  "merge_share_binary": round(b["t_merge_ms"] / tot_b, 4),
+                  "time_binary_over_flat": round(tot_b / tot_f, 4),
+                  "peak_list_bytes_binary_over_flat": round(b["peak_list_bytes"] / f["peak_list_bytes"], 4)})
+
+
+def bench_batched(args, sample=300, seed=5):
+    """MCL to convergence over the 20,000-component block-diagonal graph:
+    all components per call (converged ones frozen) vs one component at a
+    time (timed on a random sample of components, scaled to all)."""
+    import numpy as np
+    import torch
+    from mclgen import config3_graph
+    from paper_2002_10083_amd import drivers, mcl, tuning
+    t0 = time.time()
+    U = config3_graph()
+    log("generated %d components, n=%d nnz=%d in %.1f s" % (len(U.comp_ptr) - 1, U.ncols, U.nnz,
+                                                           time.time() - t0))
+    A = mcl.DeviceCSC.from_host(U)
+    mcl.normalize_(A)
+    comp = torch.from_numpy(U.comp_ptr).cuda()
+    policy, scale, keys = tuning.load_policy("iterate")
+    params = mcl.default_params(bin_policy=policy, est_scale=scale, cohen_keys=keys)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Af, iters, info = drivers.batched_mcl(A, comp, params)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t
+    # per-component loop on a sample (host copy of the normalised matrix)
+    An = A.to_host()
+    ncomp = len(U.comp_ptr) - 1
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(ncomp, size=min(sample, ncomp), replace=False))
+    t_loop = 0.0
+    same = True
+    for c in pick:
+        c0, c1 = int(U.comp_ptr[c]), int(U.comp_ptr[c + 1])
+        blk = mcl.DeviceCSC.from_host(drivers.component_block(An, c0, c1))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Bf, it = drivers.component_mcl(blk, params)
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t
+        same &= bool(it == iters[c]) and drivers.same_block(Af, c0, c1, Bf)
+    est_loop = t_loop * ncomp / len(pick)
+    return _line("MCL to convergence over 20,000 components: batched speedup over the per-component loop",
+                 round(est_loop / t_batched, 3), "x", t_batched * 1e3, True,
+                 "block-diagonal planted graph, 20,000 components of 8..30,000 vertices (seed 1003)",
+                 {"n": U.ncols, "nnz": U.nnz, "components": ncomp, "batched_s": round(t_batched, 3),
+                  "batched_calls": info["calls"], "iterations_max": int(iters.max()),
+                  "iterations_mean": round(float(iters.mean()), 2),
+                  "loop_sample_components": int(len(pick)), "loop_sample_s": round(t_loop, 3),
+                  "loop_estimated_s": round(est_loop, 3), "sample_bit_identical": bool(same)})
+
+
+def bench_mlp(args, train_seeds=(2001, 2002, 2003), n_train=250_000):
+    """Learned table sizing: train the 12-64-64-1 MLP on other seeds with the
+    library's kernels, then compare the fused iteration on the 1M-vertex graph
+    with Cohen sizing (same output, different overflow and time)."""
+    import numpy as np
+    import torch
+    from mclgen import config1_graph
+    from paper_2002_10083_amd import learned, mcl, tuning
+    policy, scale, keys = tuning.load_policy("iterate")
+    base = dict(bin_policy=policy, est_scale=scale, cohen_keys=keys)
+    Xs, ys = [], []
+    t = time.time()
+    for sd in train_seeds:
+        Wt = config1_graph(seed=sd, n=n_train, n_clusters=n_train // 20)
+        At = mcl.DeviceCSC.from_host(Wt)
+        mcl.normalize_(At)
+        X, y = learned.collect(At, iterations=4, params=mcl.default_params(**base))
+        Xs.append(X)
+        ys.append(y)
+    X, y = torch.cat(Xs), torch.cat(ys)
+    t_collect = time.time() - t
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    state, packed, losses = learned.train(X, y, epochs=6, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    rows_per_s = X.shape[0] * 6 / t_train
+    W = config1_graph(n=args.n, n_clusters=max(1, args.n // 20))
+    A = mcl.DeviceCSC.from_host(W)
+    mcl.normalize_(A)
+    runs = {}
+    # Cohen runs with its tuned margin; the MLP margin is picked the same way
+    # (by step time) from a short list
+    trials = [("cohen", dict(estimator=mcl.EST_COHEN))]
+    trials += [("mlp", dict(estimator=mcl.EST_MLP, mlp_weights=packed, est_scale=sc)) for sc in (0.8, 1.0, 1.25)]
+    for name, kw in trials:
+        best = runs.get(name)
+        for _ in range(3):
+            G, ch, st = mcl.iterate(A, mcl.default_params(**dict(base, **kw)))
+            st["est_scale"] = kw.get("est_scale", scale)
+            if best is None or st["t_total_ms"] < best[1]["t_total_ms"]:
+                best = (G, st)
+        runs[name] = best
+    same = (torch.equal(runs["cohen"][0].rowidx, runs["mlp"][0].rowidx)
+            and torch.equal(runs["cohen"][0].val, runs["mlp"][0].val))
+    acc = learned.evaluate(packed, A)
+    sc, sm = runs["cohen"][1], runs["mlp"][1]
+    pick = ("t_total_ms", "t_numeric_ms", "t_fallback_ms", "n_overflow", "n_global", "est_scale")
+    return _line("fused MCL iteration at n=1M: speedup of learned (MLP) table sizing over Cohen",
+                 round(sc["t_total_ms"] / sm["t_total_ms"], 4), "x", sm["t_total_ms"], True,
+                 "one fused MCL iteration on the 1M-vertex planted graph (seed 1001); MLP trained on "
+                 "seeds %s at n=%d" % (list(train_seeds), n_train),
+                 {"cohen": {k: sc[k] for k in pick}, "mlp": {k: sm[k] for k in pick},
+                  "bit_identical": bool(same), "train_rows": int(X.shape[0]),
+                  "train_rows_per_s": round(rows_per_s, 1), "collect_s": round(t_collect, 1),
+                  "train_s": round(t_train, 2), "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)],
+                  "log_error": acc}, dtype="bf16/f32 MLP, f64 expansion")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,11 +255,22 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="iterate", choices=["iterate", "merge", "batched", "mlp"],
+                    help="iterate: one fused iteration at n=1M (default); merge: 8 SUMMA-stage "
+                         "partials merged by Alg. 2 vs one flat merge; batched: MCL to convergence "
+                         "over 20,000 components, batched vs per component; mlp: learned vs Cohen "
+                         "table sizing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload != "iterate":
+        import torch
+        torch.cuda.set_device(0)
+        out = {"merge": bench_merge, "batched": bench_batched, "mlp": bench_mlp}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     import numpy as np
     import torch

@@ -96,6 +96,10 @@ typedef struct {
     int64_t *nnz_out;        /* optional device int64[ncols]: exact nnz of each product column */
     int32_t schedule;        /* work-order flags, MCL_SCHED_* (0 = plain order); never changes
                                 results, only the order in which columns are processed */
+    int64_t phase_bytes;     /* mcl_iterate: bound on the product's temporary storage; when the
+                                planned temp exceeds it the columns are processed in phases of
+                                contiguous column ranges (same results).  0 = 40 % of the free
+                                device memory at call time; < 0 = never split */
 } mcl_params;
 
 typedef struct {
@@ -118,6 +122,7 @@ typedef struct {
     int64_t bin_flops[8];
     int64_t bin_bnnz[8];
     int64_t bin_out[8];
+    int64_t n_phases;         /* column phases used by mcl_iterate (see mcl_params.phase_bytes) */
 } mcl_stats;
 
 /* Fills `p` with the defaults: theta 1e-4, S 1100, R 1400, pct 0.9, r 2,

@@ -38,8 +38,8 @@ struct Mem {
     const mcl_allocator *al;
     hipStream_t st;
     std::vector<void *> work, outs;
+    std::vector<size_t> wsz;
     size_t cur = 0, peak = 0;
-    std::vector<size_t> sizes;
 
     void *raw(size_t bytes)
     {
@@ -61,9 +61,30 @@ struct Mem {
         size_t b = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
         void *p = raw(b);
         work.push_back(p);
+        wsz.push_back(b);
         cur += b;
         peak = std::max(peak, cur);
         return (T *)p;
+    }
+    // workspace taken after mark() can be released early with free_since()
+    size_t mark() const { return work.size(); }
+    void free_since(size_t m, const std::vector<void *> &keep)
+    {
+        std::vector<void *> kw;
+        std::vector<size_t> ks;
+        for (size_t i = m; i < work.size(); ++i) {
+            if (std::find(keep.begin(), keep.end(), work[i]) != keep.end()) {
+                kw.push_back(work[i]);
+                ks.push_back(wsz[i]);
+            } else {
+                release(work[i]);
+                cur -= wsz[i];
+            }
+        }
+        work.resize(m);
+        wsz.resize(m);
+        work.insert(work.end(), kw.begin(), kw.end());
+        wsz.insert(wsz.end(), ks.begin(), ks.end());
     }
     template <typename T>
     T *out(int64_t n)
@@ -85,6 +106,7 @@ struct Mem {
     {
         for (void *p : work) release(p);
         work.clear();
+        wsz.clear();
     }
     void free_outs()
     {
@@ -222,6 +244,7 @@ struct EngineOut {
     double bin_ms[8] = {0};
     int64_t bin_cols[8] = {0};
     int64_t bin_acc[24] = {0};  // per bin: flops, nnz(B_*j), output entries
+    int n_phases = 0;
 };
 
 mcl::BinOffsets offsets_of(const int32_t counts[8])
@@ -289,6 +312,58 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
     for (auto e : ev) (void)hipEventDestroy(e);
 }
 
+// Column ranges of a phased product: consecutive columns whose planned temp
+// (12 bytes per slot) fits `phase_bytes` (0 = 40 % of the free device
+// memory, < 0 = one phase).  Returns the cut points c_0 = 0 < ... < c_P = n
+// and, in cut_base, the temp offsets at the cuts.
+std::vector<int64_t> phase_cuts(Mem &mem, const ProductPlan &pl, int64_t n, int64_t phase_bytes,
+                                std::vector<int64_t> &cut_base)
+{
+    cut_base = {0, pl.temp_total};
+    if (phase_bytes < 0 || n <= 1) return {0, n};
+    int64_t budget = phase_bytes;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIPC(hipMemGetInfo(&fr, &tot));
+        budget = (int64_t)(0.4 * (double)fr);
+    }
+    const int64_t slots = std::max<int64_t>(budget / 12, 1);
+    if (pl.temp_total <= slots) return {0, n};
+    std::vector<int64_t> hb(n + 1);
+    HIPC(hipMemcpyAsync(hb.data(), pl.base, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+    HIPC(hipStreamSynchronize(mem.st));
+    std::vector<int64_t> cuts{0};
+    cut_base = {0};
+    int64_t c0 = 0;
+    while (c0 < n) {
+        // largest c1 with hb[c1] - hb[c0] <= slots, at least one column
+        int64_t c1 = (int64_t)(std::upper_bound(hb.begin() + c0, hb.end(), hb[c0] + slots) - hb.begin()) - 1;
+        c1 = std::min(std::max(c1, c0 + 1), n);
+        cuts.push_back(c1);
+        cut_base.push_back(hb[c1]);
+        c0 = c1;
+    }
+    return cuts;
+}
+
+// Sliced copy of the source matrix when the policy picks a sliced-table
+// launch for some bin (every other launch accepts it too: the entries of one
+// step stay distinct).
+void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
+{
+    bool sliced = false;
+    for (int b = 3; b <= 6; ++b) sliced |= mcl::lds_variant_sliced(b, (int)((policy >> (4 * b)) & 15u));
+    if (!sliced || a.A.ncols <= 0) return;
+    const int64_t nz = std::max<int64_t>(a.A.nnz, 1);
+    int32_t *ro = mem.ws<int32_t>(nz);
+    double *vo = mem.ws<double>(nz);
+    int32_t *go = mem.ws<int32_t>(a.A.ncols * 17);
+    mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
+    a.A.rowidx = ro;
+    a.A.val = vo;
+    a.goff = go;
+}
+
 // Runs the numeric phase for the columns binned in `pl`, then resolves table
 // overflow: overflowed columns move one LDS bin up and are recomputed into a
 // new temp region; columns that overflow the largest LDS bin get an exact
@@ -313,22 +388,6 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         int64_t *dummy = mem.ws<int64_t>(8);
         HIPC(hipMemsetAsync(dummy, 0xFF, 8 * sizeof(int64_t), mem.st));  // row -1 (no row)
         a.dummy = dummy;
-    }
-    // sliced copy of the source matrix when a sliced-table launch is chosen
-    // (every other launch accepts it too: entries of a step stay distinct)
-    if (!a.parts) {
-        bool sliced = false;
-        for (int b = 3; b <= 6; ++b) sliced |= mcl::lds_variant_sliced(b, (int)((policy >> (4 * b)) & 15u));
-        if (sliced && a.A.ncols > 0) {
-            const int64_t nz = std::max<int64_t>(a.A.nnz, 1);
-            int32_t *ro = mem.ws<int32_t>(nz);
-            double *vo = mem.ws<double>(nz);
-            int32_t *go = mem.ws<int32_t>(a.A.ncols * 17);
-            mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
-            a.A.rowidx = ro;
-            a.A.val = vo;
-            a.goff = go;
-        }
     }
     a.lo = pl.lo;
     a.hi = pl.hi;
@@ -625,6 +684,7 @@ int mcl_expand(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, const mcl_params 
         a.B = dB;
         a.pa = prune_args(p);
         a.xcd_order = p.schedule & MCL_SCHED_XCD;
+        use_sliced_source(mem, a, (uint32_t)p.bin_policy);
         EngineOut eo;
         engine(mem, n, A->nrows, mcl::MODE_EXPAND, a, pl, eo, tm, B->colptr, (uint32_t)p.bin_policy);
         if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, pl.cnt, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
@@ -703,17 +763,83 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
         a.delta = delta;
         a.mode = mode;
         a.xcd_order = p.schedule & MCL_SCHED_XCD;
+        const uint32_t policy = (uint32_t)p.bin_policy;
+        use_sliced_source(mem, a, policy);
+        std::vector<int64_t> cut_base;
+        const std::vector<int64_t> cuts = phase_cuts(mem, pl, n, p.phase_bytes, cut_base);
         EngineOut eo;
-        engine(mem, n, A->nrows, mcl::MODE_ITERATE, a, pl, eo, tm, A->colptr, (uint32_t)p.bin_policy);
-        if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);
-        if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, nnzp, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
-        tm.mark();
-        const size_t c0 = tm.ev.size() - 1;
         int64_t *colptr = mem.out<int64_t>(n + 1);
-        const int64_t nnz = scan_counts(mem, pl.cnt, n, colptr);
-        int32_t *row = mem.out<int32_t>(nnz);
-        double *val = mem.out<double>(nnz);
-        mcl::launch_compact(n, pl.bin, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        int32_t *row = nullptr;
+        double *val = nullptr;
+        int64_t nnz = 0;
+        size_t c0ev = 0;
+        if (cuts.size() == 2) {
+            engine(mem, n, A->nrows, mcl::MODE_ITERATE, a, pl, eo, tm, A->colptr, policy);
+            if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);
+            if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, nnzp, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+            tm.mark();
+            c0ev = tm.ev.size() - 1;
+            nnz = scan_counts(mem, pl.cnt, n, colptr);
+            row = mem.out<int32_t>(nnz);
+            val = mem.out<double>(nnz);
+            mcl::launch_compact(n, pl.bin, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        } else {
+            // phases: contiguous column ranges, each with its own temp; the
+            // kept entries of a phase are compacted into a phase buffer and
+            // the temp is released before the next phase
+            HIPC(hipMemsetAsync(pl.cnt, 0, n * sizeof(int64_t), mem.st));
+            int32_t *phb = mem.ws<int32_t>(n);
+            int64_t *phbase = mem.ws<int64_t>(n);
+            int32_t *pcnt = mem.ws<int32_t>(8);
+            struct PhaseOut { int64_t c0, c1; int64_t *cp; int32_t *r; double *v; };
+            std::vector<PhaseOut> outs;
+            for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+                const int64_t c0 = cuts[q], c1 = cuts[q + 1];
+                const size_t mk = mem.mark();
+                HIPC(hipMemsetAsync(pcnt, 0, 8 * sizeof(int32_t), mem.st));
+                mcl::launch_phase_plan(n, pl.bin, pl.base, c0, c1, phb, phbase, pcnt, mem.st);
+                ProductPlan ph = pl;
+                ph.bin = phb;
+                ph.base = phbase;
+                HIPC(hipMemcpyAsync(ph.counts, pcnt, sizeof(ph.counts), hipMemcpyDeviceToHost, mem.st));
+                HIPC(hipStreamSynchronize(mem.st));
+                ph.temp_total = cut_base[q + 1] - cut_base[q];
+                EngineOut e;
+                engine(mem, n, A->nrows, mcl::MODE_ITERATE, a, ph, e, tm, A->colptr, policy);
+                int64_t *pcp = mem.ws<int64_t>(c1 - c0 + 1);
+                const int64_t pn = scan_counts(mem, pl.cnt + c0, c1 - c0, pcp);
+                int32_t *r = mem.ws<int32_t>(pn);
+                double *v = mem.ws<double>(pn);
+                mcl::launch_compact(c1 - c0, phb + c0, phbase + c0, pl.cnt + c0, pcp, e.tr, r, v, mem.st);
+                HIPC(hipGetLastError());
+                mem.free_since(mk, {pcp, r, v});
+                outs.push_back({c0, c1, pcp, r, v});
+                eo.n_overflow += e.n_overflow;
+                eo.n_global += e.n_global;
+                eo.t_numeric += e.t_numeric;
+                eo.t_fallback += e.t_fallback;
+                for (int b = 0; b < 8; ++b) {
+                    eo.bin_ms[b] += e.bin_ms[b];
+                    eo.bin_cols[b] += e.bin_cols[b];
+                }
+                for (int b = 0; b < 24; ++b) eo.bin_acc[b] += e.bin_acc[b];
+            }
+            eo.n_phases = (int)outs.size();
+            if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);
+            if (p.nnz_out) HIPC(hipMemcpyAsync(p.nnz_out, nnzp, n * sizeof(int64_t), hipMemcpyDeviceToDevice, mem.st));
+            tm.mark();
+            c0ev = tm.ev.size() - 1;
+            nnz = scan_counts(mem, pl.cnt, n, colptr);
+            row = mem.out<int32_t>(nnz);
+            val = mem.out<double>(nnz);
+            for (const PhaseOut &o : outs) {
+                mcl::TempRegions tr{};
+                tr.row[0] = o.r;
+                tr.val[0] = o.v;
+                mcl::launch_compact(o.c1 - o.c0, pl.bin + o.c0, o.cp, pl.cnt + o.c0, colptr + o.c0, tr, row, val,
+                                    mem.st);
+            }
+        }
         if (comp_ptr) mcl::launch_copy_inactive(dA, col_comp, active, colptr, row, val, mem.st);
         HIPC(hipGetLastError());
         tm.mark();
@@ -744,9 +870,10 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
             stats->t_estimate_ms = test;
             stats->t_numeric_ms = eo.t_numeric;
             stats->t_fallback_ms = eo.t_fallback;
-            stats->t_compact_ms = tm.ms(c0, tm.ev.size() - 1);
+            stats->t_compact_ms = tm.ms(c0ev, tm.ev.size() - 1);
             stats->t_total_ms = tm.ms(0, tm.ev.size() - 1);
             stats->peak_workspace_bytes = (int64_t)mem.peak;
+            stats->n_phases = std::max(1, eo.n_phases);
         }
     });
 }

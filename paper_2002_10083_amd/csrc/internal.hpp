@@ -51,6 +51,9 @@ constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 sl
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin
 bool lds_variant_sliced(int bin, int variant);       // launch reads the sliced layout of A
+// phase [c0, c1) of a phased product: bins (-1 outside), phase-relative temp offsets, bin counts
+void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
+                       int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
 // sliced copy of A (entries of each column ordered by row group) + boundaries
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
 void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,

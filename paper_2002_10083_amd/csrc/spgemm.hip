@@ -264,6 +264,25 @@ void launch_cohen_finish(const DevCSC &, const float *, int, float *, hipStream_
 // the estimate scaled by 1.3 * est_scale (clamped to ub_j).  The bin is the
 // smallest LDS table whose capacity holds need_j; beyond 8192 slots the
 // column goes to the HBM-table kernel (bin 7) sized by need_j.
+// Wave-aggregated reservation in one of NC counters: the active lanes with
+// `valid` and class c reserve consecutive positions of counters[c] with one
+// atomic per class and wave.  Returns the lane's position (0 when !valid).
+template <int NC>
+__device__ __forceinline__ int wave_reserve(int32_t *counters, int c, bool valid)
+{
+    int pos = 0;
+    for (int q = 0; q < NC; ++q) {
+        const uint64_t m = ballot(valid && c == q);
+        if (m == 0) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane() == leader) base = atomicAdd(&counters[q], __popcll(m));
+        base = readlane_i(base, leader);
+        if (valid && c == q) pos = base + popc_below(m);
+    }
+    return pos;
+}
+
 __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__restrict__ flops,
                                               const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
                                               const float *__restrict__ est, int est_kind,
@@ -273,9 +292,11 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
                                               int32_t *__restrict__ bin_count,
                                               unsigned long long *__restrict__ max_global)
 {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        if (col_active && !col_active[j]) { bin[j] = -1; capv[j] = 0; continue; }
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = j0 + threadIdx.x;
+        const bool act = j < ncols && !(col_active && !col_active[j]);
+        if (j < ncols && !act) { bin[j] = -1; capv[j] = 0; }
+        if (!act) continue;
         const int64_t fl = flops[j];
         int64_t ub = fl;
         if (fl > 0) ub = min(ub, (int64_t)(hi[j] - lo[j] + 1));
@@ -294,7 +315,7 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
         if (b == NUM_LDS_BINS && try_lds) b = NUM_LDS_BINS - 1;
         bin[j] = b;
         capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
-        atomicAdd(&bin_count[b], 1);
+        wave_reserve<NUM_LDS_BINS + 1>(bin_count, b, true);
         if (b == NUM_LDS_BINS) atomicMax(max_global, (unsigned long long)need);
     }
 }
@@ -311,16 +332,44 @@ void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const i
                        (unsigned long long *)max_global);
 }
 
+// One phase of a phased product: columns [c0, c1) keep their bin and get
+// their temp offset relative to the phase start; all others are disabled.
+__global__ __launch_bounds__(256) void k_phase_plan(int64_t n, const int32_t *__restrict__ bin,
+                                                    const int64_t *__restrict__ base, int64_t c0, int64_t c1,
+                                                    int32_t *__restrict__ ph_bin, int64_t *__restrict__ ph_base,
+                                                    int32_t *__restrict__ counts)
+{
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < n; j0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = j0 + threadIdx.x;
+        const int b = (j >= c0 && j < c1) ? bin[j] : -1;
+        if (j < n) ph_bin[j] = b;
+        if (b >= 0) ph_base[j] = base[j] - base[c0];
+        wave_reserve<NUM_LDS_BINS + 1>(counts, b, b >= 0);
+    }
+}
+
+void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
+                       int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st)
+{
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_phase_plan, dim3(grid), dim3(256), 0, st, n, bin, base, c0, c1, ph_bin, ph_base,
+                       counts);
+}
+
 // Scatter the listed columns into per-bin lists by bin[j].
 __global__ __launch_bounds__(256) void k_scatter_bins_list(const int32_t *__restrict__ list, int32_t n,
                                                            const int32_t *__restrict__ bin,
                                                            BinOffsets bin_off, int32_t *__restrict__ cursor,
                                                            int32_t *__restrict__ out)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int j = list[i];
-        const int b = bin[j];
-        out[bin_off.off[b] + atomicAdd(&cursor[b], 1)] = j;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < n;
+        const int j = valid ? list[i] : 0;
+        const int b = valid ? bin[j] : 0;
+        const int pos = wave_reserve<NUM_LDS_BINS + 1>(cursor, b, valid);
+        if (valid) out[bin_off.off[b] + pos] = j;
     }
 }
 
@@ -366,7 +415,7 @@ __global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list
         const int b = NUM_LDS_BINS;
         bin[j] = b;
         capv[j] = need;
-        atomicAdd(&bin_count[b], 1);
+        atomicAdd(&bin_count[b], 1);  // few columns reach this path
         atomicMax(max_global, (unsigned long long)need);
     }
 }
@@ -444,16 +493,19 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
                                               int32_t *__restrict__ exact_list,
                                               int32_t *__restrict__ n_exact)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int j = list[i];
-        const int b = bin[j];
-        if (b + 1 < NUM_LDS_BINS) {
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < n;
+        const int j = valid ? list[i] : 0;
+        const int b = valid ? bin[j] : 0;
+        const bool up = valid && b + 1 < NUM_LDS_BINS;
+        if (up) {
             bin[j] = b + 1;
             capv[j] = bin_cap_c(b + 1);
-            atomicAdd(&bin_count[b + 1], 1);
-        } else {
-            exact_list[atomicAdd(n_exact, 1)] = j;
         }
+        wave_reserve<NUM_LDS_BINS + 1>(bin_count, b + 1, up);
+        const int pos = wave_reserve<1>(n_exact, 0, valid && !up);
+        if (valid && !up) exact_list[pos] = j;
     }
 }
 
@@ -503,12 +555,11 @@ __global__ __launch_bounds__(256) void k_scatter_bins(int64_t ncols, const int32
                                                       BinOffsets bin_off, int32_t *__restrict__ cursor,
                                                       int32_t *__restrict__ lists)
 {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int b = bin[j];
-        if (b < 0) continue;
-        const int pos = atomicAdd(&cursor[b], 1);
-        lists[bin_off.off[b] + pos] = (int32_t)j;
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = j0 + threadIdx.x;
+        const int b = (j < ncols) ? bin[j] : -1;
+        const int pos = wave_reserve<NUM_LDS_BINS + 1>(cursor, b, b >= 0);
+        if (b >= 0) lists[bin_off.off[b] + pos] = (int32_t)j;
     }
 }
 
@@ -1571,9 +1622,12 @@ __global__ __launch_bounds__(256) void k_collect_overflow(const int32_t *__restr
                                                           int32_t *__restrict__ list,
                                                           int32_t *__restrict__ count)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int j = cols[i];
-        if (cnt[j] < 0) list[atomicAdd(count, 1)] = j;
+    for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        const int j = (i < n) ? cols[i] : 0;
+        const bool o = (i < n) && cnt[j] < 0;
+        const int pos = wave_reserve<1>(count, 0, o);
+        if (o) list[pos] = j;
     }
 }
 

@@ -1,0 +1,165 @@
+"""Host-side drivers over the C-ABI calls (argument handling and loop control
+only; every arithmetic step runs in the library's kernels).
+
+* ``summa_merge``: the inner dimension of C = A*A is cut into ``nstages``
+  contiguous ranges K_1..K_s, stage i contributes the partial product
+  A[:, K_i] * A[K_i, :] (one SUMMA stage of one process, Section 5), and the
+  partials are merged either with the binary schedule of Alg. 2 (after stage
+  i, the top 1 + v2(i) lists of the stack are merged, v2 = number of factors
+  of two) or all at once after the last stage.  Equal rows are summed in
+  stage order.
+* ``batched_mcl`` / ``component_mcl``: MCL to convergence over a
+  block-diagonal matrix of many components, either all components in each
+  call with a per-component active mask, or one component at a time.
+"""
+from __future__ import annotations
+
+import time
+from typing import List, Sequence
+
+import numpy as np
+import torch
+
+from . import mcl
+
+
+def csc_bytes(M: "mcl.DeviceCSC") -> int:
+    return 8 * (M.ncols + 1) + 12 * M.nnz
+
+
+def stage_ranges(n: int, nstages: int):
+    """Contiguous ranges of the inner dimension, one per stage (sizes differ by <= 1)."""
+    cuts = [(n * i) // nstages for i in range(nstages + 1)]
+    return [(cuts[i], cuts[i + 1]) for i in range(nstages)]
+
+
+def column_block(A: "mcl.DeviceCSC", k0: int, k1: int) -> "mcl.DeviceCSC":
+    """A[:, k0:k1] (views of A's row and value arrays)."""
+    cp = A.colptr[k0:k1 + 1]
+    p0, p1 = int(cp[0]), int(cp[-1])
+    return mcl.DeviceCSC(A.nrows, k1 - k0, (cp - p0).contiguous(), A.rowidx[p0:p1], A.val[p0:p1])
+
+
+def row_block(A: "mcl.DeviceCSC", k0: int, k1: int) -> "mcl.DeviceCSC":
+    """A[k0:k1, :] with rows renumbered from 0 (rows stay ascending)."""
+    keep = (A.rowidx >= k0) & (A.rowidx < k1)
+    counts = torch.diff(A.colptr)
+    col = torch.repeat_interleave(torch.arange(A.ncols, device=A.colptr.device), counts)
+    per_col = torch.bincount(col[keep], minlength=A.ncols)
+    cp = torch.zeros(A.ncols + 1, dtype=torch.int64, device=A.colptr.device)
+    cp[1:] = torch.cumsum(per_col, 0)
+    return mcl.DeviceCSC(k1 - k0, A.ncols, cp, (A.rowidx[keep] - k0).to(torch.int32).contiguous(),
+                         A.val[keep].contiguous())
+
+
+def binary_schedule(nstages: int) -> List[int]:
+    """Lists merged after each stage by Alg. 2 (0 = none)."""
+    out = []
+    for i in range(1, nstages + 1):
+        v = (i & -i).bit_length() - 1
+        out.append(v + 1 if v > 0 else 0)
+    return out
+
+
+def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", params=None):
+    """C = sum over stages of A[:, K_i] A[K_i, :], merged per `schedule`
+    ("binary" = Alg. 2, "flat" = one merge of all partials at the end).
+    Returns (C, info) with expansion and merge times (ms), the peak bytes held
+    by partial and merged lists, and the per-stage list sizes."""
+    if schedule not in ("binary", "flat"):
+        raise ValueError(schedule)
+    stack: List[mcl.DeviceCSC] = []
+    live = peak = 0
+    t_exp = t_mrg = 0.0
+    sizes = []
+    merges = []
+
+    def merge(lists):
+        nonlocal live, peak, t_mrg
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        M, _ = mcl.merge_partials(lists)
+        torch.cuda.synchronize()
+        t_mrg += (time.perf_counter() - t) * 1e3
+        peak = max(peak, live + csc_bytes(M))
+        live += csc_bytes(M) - sum(csc_bytes(x) for x in lists)
+        merges.append(len(lists))
+        return M
+
+    plan = binary_schedule(nstages)
+    for i, (k0, k1) in enumerate(stage_ranges(A.ncols, nstages), start=1):
+        Ak = column_block(A, k0, k1)
+        Bk = row_block(A, k0, k1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P, _ = mcl.expand(Ak, Bk, params)
+        torch.cuda.synchronize()
+        t_exp += (time.perf_counter() - t) * 1e3
+        del Ak, Bk
+        stack.append(P)
+        sizes.append(P.nnz)
+        live += csc_bytes(P)
+        peak = max(peak, live)
+        if schedule == "binary" and plan[i - 1] > 0:
+            take = stack[-plan[i - 1]:]
+            del stack[-plan[i - 1]:]
+            stack.append(merge(take))
+            del take
+    if len(stack) > 1:
+        M = merge(stack)
+        stack = [M]
+    C = stack[0]
+    return C, dict(t_expand_ms=t_exp, t_merge_ms=t_mrg, peak_list_bytes=peak, partial_nnz=sizes,
+                   merges=merges, nnz=C.nnz)
+
+
+def batched_mcl(A: "mcl.DeviceCSC", comp_ptr: torch.Tensor, params=None, tol: float = 1e-9,
+                max_iter: int = 200):
+    """Iterate every component until its change drops below `tol`; converged
+    components are frozen (copied) by the library.  Returns (A_final,
+    iterations per component, info)."""
+    ncomp = comp_ptr.numel() - 1
+    active = torch.ones(ncomp, dtype=torch.uint8, device=comp_ptr.device)
+    iters = np.zeros(ncomp, np.int64)
+    steps = []
+    it = 0
+    while it < max_iter:
+        t = time.perf_counter()
+        A, change, st = mcl.iterate(A, params, comp_ptr=comp_ptr, active=active)
+        steps.append(dict(ms=(time.perf_counter() - t) * 1e3, active=int(active.sum()), flops=st["flops"]))
+        act = active.cpu().numpy().astype(bool)
+        iters[act] += 1
+        still = act & (change >= tol)
+        it += 1
+        if not still.any():
+            break
+        active = torch.from_numpy(still.astype(np.uint8)).to(comp_ptr.device)
+    return A, iters, dict(calls=it, steps=steps)
+
+
+def component_block(W, c0: int, c1: int):
+    """Host CSC of the diagonal block [c0, c1) of a block-diagonal matrix, rows renumbered."""
+    from mclgen import CSC
+    p0, p1 = int(W.colptr[c0]), int(W.colptr[c1])
+    return CSC(c1 - c0, c1 - c0, (W.colptr[c0:c1 + 1] - p0).astype(np.int64),
+               (W.rowidx[p0:p1] - c0).astype(np.int32), W.val[p0:p1].copy())
+
+
+def component_mcl(Ablk: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 200):
+    """Plain loop on one component: iterate until the change drops below `tol`."""
+    it = 0
+    while it < max_iter:
+        Ablk, change, _ = mcl.iterate(Ablk, params)
+        it += 1
+        if change < tol:
+            break
+    return Ablk, it
+
+
+def same_block(Abig: "mcl.DeviceCSC", c0: int, c1: int, Ablk: "mcl.DeviceCSC") -> bool:
+    """Is the diagonal block [c0, c1) of Abig (all its columns' entries lie in
+    the block) bit-identical to Ablk?"""
+    p0, p1 = int(Abig.colptr[c0]), int(Abig.colptr[c1])
+    cp = Abig.colptr[c0:c1 + 1] - p0
+    return (torch.equal(cp, Ablk.colptr) and torch.equal(Abig.rowidx[p0:p1] - c0, Ablk.rowidx)
+            and torch.equal(Abig.val[p0:p1], Ablk.val))

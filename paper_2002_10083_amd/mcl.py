@@ -60,7 +60,8 @@ class Params(ctypes.Structure):
                 ("iteration", ctypes.c_int32), ("est_scale", ctypes.c_double),
                 ("mlp_weights", ctypes.c_void_p), ("validate", ctypes.c_int32),
                 ("bin_policy", ctypes.c_int32), ("est_out", ctypes.c_void_p),
-                ("nnz_out", ctypes.c_void_p), ("schedule", ctypes.c_int32)]
+                ("nnz_out", ctypes.c_void_p), ("schedule", ctypes.c_int32),
+                ("phase_bytes", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -75,7 +76,7 @@ class Stats(ctypes.Structure):
                 ("peak_workspace_bytes", ctypes.c_int64),
                 ("bin_cols", ctypes.c_int64 * 8), ("bin_ms", ctypes.c_double * 8),
                 ("bin_flops", ctypes.c_int64 * 8), ("bin_bnnz", ctypes.c_int64 * 8),
-                ("bin_out", ctypes.c_int64 * 8)]
+                ("bin_out", ctypes.c_int64 * 8), ("n_phases", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}

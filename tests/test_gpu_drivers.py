@@ -1,0 +1,81 @@
+"""GPU drivers against the oracle: SUMMA-stage partial products merged with
+the binary schedule of Alg. 2 (and with one flat merge), and batched MCL to
+convergence against the per-component loop."""
+import numpy as np
+import pytest
+
+import oracle
+from mclgen import CSC, planted_components, planted_graph
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def drv():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_10083_amd import drivers, mcl
+    return drivers, mcl
+
+
+def _stage_partials(A, nstages, drivers):
+    S = A.to_scipy()
+    parts = []
+    for k0, k1 in drivers.stage_ranges(A.ncols, nstages):
+        Ak = CSC.from_scipy(S[:, k0:k1])
+        Bk = CSC.from_scipy(S[k0:k1, :])
+        parts.append(oracle.expand(Ak, Bk)[0])
+    return parts
+
+
+@pytest.mark.parametrize("nstages", [8, 5])
+def test_summa_merge_matches_oracle(drv, nstages):
+    drivers, mcl = drv
+    A = oracle.normalize(planted_graph(3000, 120, s_cap=300, seed=41))
+    parts = _stage_partials(A, nstages, drivers)
+    dA = mcl.DeviceCSC.from_host(A)
+    for schedule, ref in (("binary", oracle.binary_merge(parts)[0]), ("flat", oracle.merge(parts))):
+        C, info = drivers.summa_merge(dA, nstages, schedule)
+        g = C.to_host()
+        assert np.array_equal(g.colptr, ref.colptr)
+        assert np.array_equal(g.rowidx, ref.rowidx)
+        assert np.array_equal(g.val, ref.val)
+        assert info["partial_nnz"] == [p.nnz for p in parts]
+    # the merged pattern is the pattern of A*A; values agree to rounding
+    direct, _, _ = oracle.expand(A, A)
+    assert np.array_equal(g.rowidx, direct.rowidx)
+    assert np.allclose(g.val, direct.val, rtol=1e-13, atol=0)
+
+
+def test_summa_stage_blocks(drv):
+    drivers, mcl = drv
+    A = oracle.normalize(planted_graph(2000, 80, s_cap=200, seed=42))
+    S = A.to_scipy()
+    dA = mcl.DeviceCSC.from_host(A)
+    for k0, k1 in drivers.stage_ranges(A.ncols, 3):
+        for got, ref in ((drivers.column_block(dA, k0, k1), S[:, k0:k1]),
+                         (drivers.row_block(dA, k0, k1), S[k0:k1, :])):
+            r = CSC.from_scipy(ref)
+            g = got.to_host()
+            assert (g.nrows, g.ncols) == (r.nrows, r.ncols)
+            assert np.array_equal(g.colptr, r.colptr)
+            assert np.array_equal(g.rowidx, r.rowidx)
+            assert np.array_equal(g.val, r.val)
+
+
+def test_batched_mcl_equals_component_loop(drv):
+    drivers, mcl = drv
+    U = planted_components([300, 40, 1200, 8, 900, 3], [12, 2, 50, 1, 36, 1], s_cap=300, seed=43)
+    A = oracle.normalize(U)
+    comp = torch.from_numpy(U.comp_ptr).cuda()
+    Af, iters, info = drivers.batched_mcl(mcl.DeviceCSC.from_host(A), comp)
+    assert info["calls"] == iters.max()
+    for c in range(len(U.comp_ptr) - 1):
+        c0, c1 = int(U.comp_ptr[c]), int(U.comp_ptr[c + 1])
+        blk = mcl.DeviceCSC.from_host(drivers.component_block(A, c0, c1))
+        Bf, it = drivers.component_mcl(blk)
+        assert it == iters[c], c
+        assert drivers.same_block(Af, c0, c1, Bf), c
+    # clusters of the batched result are the oracle's clusters of the same matrix
+    lab = oracle.clusters(Af.to_host())
+    assert len(lab) == A.ncols

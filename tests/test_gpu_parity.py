@@ -330,3 +330,28 @@ def test_allocator_failure_releases_everything(mcl):
         assert len(al.live) == 0
     G, _, _ = mcl.iterate(dA)     # still usable afterwards
     assert G.nnz > 0
+
+
+def test_phased_iterate_is_identical(mcl):
+    A = oracle.normalize(planted_graph(8000, 250, s_cap=900, seed=23))
+    dA = up(mcl, A)
+    ref, c0, st0 = mcl.iterate(dA, phase_bytes=-1)
+    assert st0["n_phases"] == 1
+    for pb in (3 << 20, 400 << 10):
+        X, c1, st = mcl.iterate(dA, phase_bytes=pb)
+        assert st["n_phases"] > 1
+        assert torch.equal(X.colptr, ref.colptr) and torch.equal(X.rowidx, ref.rowidx)
+        assert torch.equal(X.val, ref.val) and c1 == c0
+        assert st["nnz_product"] == st0["nnz_product"] and st["flops"] == st0["flops"]
+
+
+def test_phased_batched_iterate_is_identical(mcl):
+    U = planted_components([300, 40, 2000, 8, 900, 1500], [12, 2, 80, 1, 36, 60], s_cap=300, seed=24)
+    dA = up(mcl, oracle.normalize(U))
+    comp = torch.from_numpy(U.comp_ptr).cuda()
+    active = torch.tensor([1, 0, 1, 1, 0, 1], dtype=torch.uint8, device="cuda")
+    ref, c0, _ = mcl.iterate(dA, comp_ptr=comp, active=active, phase_bytes=-1)
+    X, c1, st = mcl.iterate(dA, comp_ptr=comp, active=active, phase_bytes=256 << 10)
+    assert st["n_phases"] > 1
+    assert torch.equal(X.colptr, ref.colptr) and torch.equal(X.rowidx, ref.rowidx)
+    assert torch.equal(X.val, ref.val) and np.array_equal(c0, c1)
