@@ -230,6 +230,7 @@ struct ProductPlan {
     int64_t *capv = nullptr;
     int64_t *base = nullptr;  // n+1
     int64_t *cnt = nullptr;
+    uint8_t *hbm_only = nullptr;  // columns sized by an exact count (HBM-table kernel)
     int32_t *lists = nullptr;
     int32_t counts[8] = {0};
     int64_t max_global = 0;
@@ -279,6 +280,14 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
                 if (variant >= mcl::lds_bin_variants(b)) variant = 0;
                 mcl::launch_numeric_lds(b, variant, mode, a, mem.st);
             } else {
+                // multi-pass LDS kernel for the columns within its capacity,
+                // HBM-resident tables for the rest
+                if (mode != mcl::MODE_COUNT && a.goff && !a.parts) {
+                    const size_t mslab = mcl::mpass_slab_bytes();
+                    const int mslabs = std::min<int>(c, 512);
+                    char *ms = mem.ws<char>((int64_t)(mslab * mslabs));
+                    mcl::launch_numeric_mpass(mode, a, ms, mslab, mslabs, mem.st);
+                }
                 const int64_t S = next_pow2((max_global * 4) / 3 + 2);
                 if (S > (int64_t)1 << 30) fail(MCL_EINVAL, "product column too large for the HBM table");
                 const int cap = (int)std::min<int64_t>((S * 3) / 4, max_global);
@@ -346,18 +355,17 @@ std::vector<int64_t> phase_cuts(Mem &mem, const ProductPlan &pl, int64_t n, int6
     return cuts;
 }
 
-// Sliced copy of the source matrix when the policy picks a sliced-table
-// launch for some bin (every other launch accepts it too: the entries of one
-// step stay distinct).
+// Sliced copy of the source matrix, read by the sliced-table and multi-pass
+// kernels (every other launch accepts it too: the entries of one step stay
+// distinct).
 void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
 {
-    bool sliced = false;
-    for (int b = 3; b <= 6; ++b) sliced |= mcl::lds_variant_sliced(b, (int)((policy >> (4 * b)) & 15u));
-    if (!sliced || a.A.ncols <= 0) return;
+    (void)policy;  // the multi-pass kernel of the largest columns needs it too
+    if (a.A.ncols <= 0) return;
     const int64_t nz = std::max<int64_t>(a.A.nnz, 1);
     int32_t *ro = mem.ws<int32_t>(nz);
     double *vo = mem.ws<double>(nz);
-    int32_t *go = mem.ws<int32_t>(a.A.ncols * 17);
+    int32_t *go = mem.ws<int32_t>(a.A.ncols * (mcl::SLICE_GROUPS + 1));
     mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
     a.A.rowidx = ro;
     a.A.val = vo;
@@ -391,6 +399,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     }
     a.lo = pl.lo;
     a.hi = pl.hi;
+    a.hbm_only = pl.hbm_only;
     a.out_base = pl.base;
     a.capv = pl.capv;
     a.out_row = trow;
@@ -459,7 +468,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
             HIPC(hipMemsetAsync(dev_l, 0, 4 * sizeof(int64_t), mem.st));
             int32_t *bc2 = mem.ws<int32_t>(8);
             HIPC(hipMemsetAsync(bc2, 0, 8 * sizeof(int32_t), mem.st));
-            mcl::launch_replan(exact, nexact, pl.cnt, pl.bin, pl.capv, bc2, dev_l, mem.st);
+            mcl::launch_replan(exact, nexact, pl.cnt, pl.bin, pl.capv, pl.hbm_only, bc2, dev_l, mem.st);
             int32_t hb2[8];
             HIPC(hipMemcpyAsync(hb2, bc2, sizeof(hb2), hipMemcpyDeviceToHost, mem.st));
             HIPC(hipMemcpyAsync(&max_need, dev_l, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
@@ -524,6 +533,8 @@ void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mc
     pl.base = mem.ws<int64_t>(n + 1);
     pl.cnt = mem.ws<int64_t>(n);
     pl.lists = mem.ws<int32_t>(n);
+    pl.hbm_only = mem.ws<uint8_t>(n);
+    HIPC(hipMemsetAsync(pl.hbm_only, 0, n, mem.st));
     tm.mark();
     const size_t e0 = tm.ev.size() - 1;
     const float *colmin = nullptr;
@@ -969,6 +980,8 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
         pl.base = mem.ws<int64_t>(n + 1);
         pl.cnt = mem.ws<int64_t>(n);
         pl.lists = mem.ws<int32_t>(n);
+        pl.hbm_only = mem.ws<uint8_t>(n);
+        HIPC(hipMemsetAsync(pl.hbm_only, 0, n, mem.st));
         mcl::launch_merge_plan(dparts, nparts, n, pl.flops, pl.lo, pl.hi, mem.st);
         int32_t *bc = mem.ws<int32_t>(8);
         int64_t *mg = mem.ws<int64_t>(1);

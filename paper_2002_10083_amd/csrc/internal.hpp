@@ -43,15 +43,21 @@ struct NumericArgs {
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     int32_t xcd_order;        // nonzero: contiguous runs of the column list per XCD
-    const int32_t *goff;      // sliced layout of A: 17 group boundaries per column (or null)
+    const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
+    const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
 };
 
 // ---- spgemm.hip
+constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced source layout
 constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin
 bool lds_variant_sliced(int bin, int variant);       // launch reads the sliced layout of A
 // phase [c0, c1) of a phased product: bins (-1 outside), phase-relative temp offsets, bin counts
+// largest columns: multi-pass LDS accumulation + sort/epilogue in HBM scratch
+size_t mpass_slab_bytes();
+void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
+                          hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
 // sliced copy of A (entries of each column ordered by row group) + boundaries
@@ -75,7 +81,7 @@ void launch_scatter_bins_list(const int32_t *list, int32_t n, const int32_t *bin
 void launch_bound_estimate(int64_t n, const int64_t *flops, const int32_t *lo, const int32_t *hi,
                            int64_t nrows, float *est, hipStream_t st);
 void launch_replan(const int32_t *list, int32_t n, const int64_t *exact, int32_t *bin, int64_t *capv,
-                   int32_t *bin_count, int64_t *max_global, hipStream_t st);
+                   uint8_t *hbm_only, int32_t *bin_count, int64_t *max_global, hipStream_t st);
 void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, const int32_t *lo,
                        const int32_t *hi, int64_t nrows, int64_t *ub, int64_t *max_ub, hipStream_t st);
 void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,

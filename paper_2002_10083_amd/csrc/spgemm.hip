@@ -406,6 +406,7 @@ void launch_bound_estimate(int64_t n, const int64_t *flops, const int32_t *lo, c
 __global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list, int32_t n,
                                                 const int64_t *__restrict__ exact,
                                                 int32_t *__restrict__ bin, int64_t *__restrict__ capv,
+                                                uint8_t *__restrict__ hbm_only,
                                                 int32_t *__restrict__ bin_count,
                                                 unsigned long long *__restrict__ max_global)
 {
@@ -415,17 +416,18 @@ __global__ __launch_bounds__(256) void k_replan(const int32_t *__restrict__ list
         const int b = NUM_LDS_BINS;
         bin[j] = b;
         capv[j] = need;
+        hbm_only[j] = 1;
         atomicAdd(&bin_count[b], 1);  // few columns reach this path
         atomicMax(max_global, (unsigned long long)need);
     }
 }
 
 void launch_replan(const int32_t *list, int32_t n, const int64_t *exact, int32_t *bin, int64_t *capv,
-                   int32_t *bin_count, int64_t *max_global, hipStream_t st)
+                   uint8_t *hbm_only, int32_t *bin_count, int64_t *max_global, hipStream_t st)
 {
     if (n <= 0) return;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_replan, dim3(grid), dim3(256), 0, st, list, n, exact, bin, capv, bin_count,
+    hipLaunchKernelGGL(k_replan, dim3(grid), dim3(256), 0, st, list, n, exact, bin, capv, hbm_only, bin_count,
                        (unsigned long long *)max_global);
 }
 
@@ -1241,10 +1243,10 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 // ---------------------------------------------------------------------------
 // Sliced source layout and the sliced-table kernel for large columns.
 //
-// Rows are dealt to NG = 16 groups by the top four bits of their
+// Rows are dealt to NG = 64 groups by the top six bits of their
 // multiplicative hash.  The sliced copy of a source matrix keeps every column
 // in place but orders its entries by group (rows ascending inside a group)
-// and records the 17 group boundaries of the column.  A workgroup of NW
+// and records the 65 group boundaries of the column.  A workgroup of NW
 // waves then gives wave w the groups [w*G, (w+1)*G), G = NG/NW, with a
 // private table of SW slots: the entries of A_*k that wave w needs are one
 // contiguous, exactly known run, waves never share a row, so accumulation
@@ -1252,12 +1254,13 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 // keeps the ascending-k order of every row.  Hashed groups spread the rows
 // of a column evenly over the waves whatever the vertex numbering.
 // ---------------------------------------------------------------------------
-constexpr int NG = 16;
+constexpr int NG = SLICE_GROUPS;
+static_assert(NG == WAVE, "one group per lane in the layout pass");
 
 __device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * 2654435761u; }
-__device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >> 28); }
+__device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >> 26); }
 // home bucket inside a sub-table of 2^logNB buckets: the hash bits below the group bits
-__device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return (row_hash(r) << 4) >> (32 - logNB); }
+__device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return (row_hash(r) << 6) >> (32 - logNB); }
 
 // One wave per column: group sizes, boundaries, then a stable scatter.
 __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restrict__ rowo,
@@ -1267,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
     if (k >= A.ncols) return;
     const int64_t p0 = A.colptr[k];
     const int len = (int)(A.colptr[k + 1] - p0);
-    int cnt = 0;  // lane g < NG: size of group g
+    int cnt = 0;  // lane g: size of group g
     for (int c = 0; c < len; c += WAVE) {
         const int e = c + lane();
         const int g = (e < len) ? row_group(A.rowidx[p0 + e]) : NG;
@@ -1276,9 +1279,9 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
             if (lane() == q) cnt += n;
         }
     }
-    const int own = (lane() < NG) ? cnt : 0;
-    int cur = wave_incl_scan(own) - own;  // lane g: first position of group g; lane NG: len
-    if (lane() <= NG) goff[k * (NG + 1) + lane()] = cur;
+    int cur = wave_incl_scan(cnt) - cnt;  // lane g: first position of group g
+    goff[k * (NG + 1) + lane()] = cur;
+    if (lane() == 0) goff[k * (NG + 1) + NG] = len;
     for (int c = 0; c < len; c += WAVE) {
         const int e = c + lane();
         const bool in = e < len;
@@ -1311,43 +1314,21 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
                        goff);
 }
 
-template <int NW, int SW, int MODE, int D>
-__global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
+// One wave accumulates the row groups [g0, g1) of column j into its private
+// table of SW slots (cleared here).  Returns the number of keys it placed;
+// *wovf is raised when a probe fails; more than capw keys stop the
+// accumulation early (the caller treats both as overflow).
+template <int SW, int MODE, int D>
+__device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1, int32_t *wkey, double *wval,
+                                int *wovf, int capw, double *never)
 {
-    constexpr int NT = NW * WAVE;
-    constexpr int G = NG / NW;                 // groups per wave
-    constexpr int CAPW = (13 * SW) / 16;       // keys per wave table
-    constexpr int NBW = SW / 4;                // buckets per wave table
+    constexpr int NBW = SW / 4;
     constexpr int LOGNBW = __builtin_ctz(NBW);
-    constexpr int STOT = NW * SW;
-    constexpr int CAPT = NW * CAPW;
-    constexpr int NBS = STOT / 4;              // sort buckets
-    constexpr int NBLK = CAPT / WAVE + 2;
-    static_assert(NG % NW == 0 && STOT <= 65536, "layout");
-    struct alignas(16) Sh {
-        double val[STOT];
-        int32_t key[STOT];
-        double p0[NBLK], p1[NBLK];
-        int32_t ip[NBLK];
-        int32_t bcnt[NBS], bcur[NBS];
-        int32_t hist[256];
-        uint16_t list[CAPT], sorted[CAPT];
-        int32_t wcnt[NW], wovf[NW];
-        int32_t misc[16];
-        double dmisc[4];
-        int32_t wsum[NW];
-    };
-    __shared__ Sh sh __attribute__((aligned(16)));
-    const int tid = threadIdx.x;
-    const int w = tid / WAVE;
-    const int64_t j = a.cols[blockIdx.x];
-    int32_t *wkey = sh.key + w * SW;
-    double *wval = sh.val + w * SW;
     for (int s = lane(); s < SW; s += WAVE) {
         wkey[s] = EMPTY_KEY;
         if (MODE != MODE_COUNT) wval[s] = 0.0;
     }
-    if (lane() == 0) sh.wovf[w] = 0;
+    if (lane() == 0) *wovf = 0;
     group_sync<WAVE>();
 
     const int32_t *dummy_r = (const int32_t *)a.dummy;
@@ -1368,9 +1349,9 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
             const int k = a.B.rowidx[bs + t];
             bv = a.B.val[bs + t];
             const int32_t *go = a.goff + (int64_t)k * (NG + 1);
-            const int g0 = go[w * G], g1 = go[(w + 1) * G];
-            ws = a.A.colptr[k] + g0;
-            len = g1 - g0;
+            const int r0 = go[g0], r1 = go[g1];
+            ws = a.A.colptr[k] + r0;
+            len = r1 - r0;
         }
         const int nch = (len + WAVE - 1) / WAVE;
         const int cpre = wave_incl_scan(nch) - nch;
@@ -1405,7 +1386,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
             for (int i = 0; i < D; ++i) {
                 int sl = -1;
                 bool fresh = false;
-                if (rr[i] >= 0) sl = place_key<true>(wkey, rr[i], hb[i], kb[i], NBW - 1, &sh.wovf[w], fresh);
+                if (rr[i] >= 0) sl = place_key<true>(wkey, rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
                 keys_w += __popcll(ballot(fresh));
                 if (MODE != MODE_COUNT) {
                     // `sink` keeps the value load out of the branch
@@ -1415,14 +1396,49 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
                 }
             }
             group_sync<WAVE>();
-            overflow = sh.wovf[w] != 0 || keys_w > CAPW;
+            overflow = *wovf != 0 || keys_w > capw;
         }
     }
+    if (MODE != MODE_COUNT && sink == -1.0) *never = sink;  // never: products are >= 0 or NaN
+    return keys_w;
+}
+
+template <int NW, int SW, int MODE, int D>
+__global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
+{
+    constexpr int NT = NW * WAVE;
+    constexpr int G = NG / NW;                 // groups per wave
+    constexpr int CAPW = (13 * SW) / 16;       // keys per wave table
+    constexpr int NBW = SW / 4;                // buckets per wave table
+    constexpr int LOGNBW = __builtin_ctz(NBW);
+    constexpr int STOT = NW * SW;
+    constexpr int CAPT = NW * CAPW;
+    constexpr int NBS = STOT / 4;              // sort buckets
+    constexpr int NBLK = CAPT / WAVE + 2;
+    static_assert(NG % NW == 0 && STOT <= 65536, "layout");
+    struct alignas(16) Sh {
+        double val[STOT];
+        int32_t key[STOT];
+        double p0[NBLK], p1[NBLK];
+        int32_t ip[NBLK];
+        int32_t bcnt[NBS], bcur[NBS];
+        int32_t hist[256];
+        uint16_t list[CAPT], sorted[CAPT];
+        int32_t wcnt[NW], wovf[NW];
+        int32_t misc[16];
+        double dmisc[4];
+        int32_t wsum[NW];
+    };
+    __shared__ Sh sh __attribute__((aligned(16)));
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    const int64_t j = a.cols[blockIdx.x];
+    const int keys_w = slice_accumulate<SW, MODE, D>(a, j, w * G, (w + 1) * G, sh.key + w * SW, sh.val + w * SW,
+                                                     &sh.wovf[w], CAPW, &sh.dmisc[3]);
     if (lane() == 0) {
         sh.wcnt[w] = keys_w;
         if (keys_w > CAPW) sh.wovf[w] = 1;
     }
-    if (MODE != MODE_COUNT && sink == -1.0) sh.dmisc[3] = sink;  // never: products are >= 0 or NaN
     __syncthreads();
 
     int m = 0, ovf = 0;
@@ -1439,6 +1455,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
+    const int64_t bs = a.B.colptr[j];
+    const int mj = (int)(a.B.colptr[j + 1] - bs);
     const int32_t lo = a.lo[j];
     const int64_t span = (int64_t)a.hi[j] - lo + 1;
     const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
@@ -1461,6 +1479,170 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
         const int s = find_from<true>(sh.key + ow * SW, k, sub_bucket(k, LOGNBW), NBW - 1);
         return (s < 0) ? -1 : ow * SW + s;
     });
+}
+
+// ---------------------------------------------------------------------------
+// Columns too large for one LDS table set: P = 2 or 4 passes of 16 waves,
+// pass p covering the row groups [p*64/P, (p+1)*64/P) (disjoint row sets, so
+// every row is accumulated in exactly one pass, in ascending k).  Each pass
+// appends its keys and values, unsorted, to the column's output slot; the
+// finishing kernel below sorts them and runs the epilogue.
+// ---------------------------------------------------------------------------
+constexpr int MP_NW = 16, MP_SW = 512;
+constexpr int MP_CAPW = (13 * MP_SW) / 16;
+// keys a column may be planned with per pass (headroom for the uneven
+// spread of rows over the 16 waves)
+constexpr int64_t MP_PASS_PLAN = (int64_t)MP_NW * MP_CAPW * 4 / 5;
+constexpr int64_t MP_MAX = 4 * MP_PASS_PLAN;
+
+__device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j)
+{
+    return a.goff && a.capv && !(a.hbm_only && a.hbm_only[j]) && a.capv[j] <= MP_MAX;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
+{
+    constexpr int STOT = MP_NW * MP_SW;
+    struct alignas(16) Sh {
+        double val[STOT];
+        int32_t key[STOT];
+        int32_t wcnt[MP_NW], wovf[MP_NW];
+        double dmisc[4];
+    };
+    __shared__ Sh sh __attribute__((aligned(16)));
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    const int64_t j = a.cols[blockIdx.x];
+    if (!multipass_column(a, j)) return;  // whole workgroup
+    const int64_t capv = a.capv[j];
+    const int P = (capv <= 2 * MP_PASS_PLAN) ? 2 : 4;
+    const int gpw = NG / (MP_NW * P);  // groups per wave and pass
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    int64_t off = 0;
+    for (int p = 0; p < P; ++p) {
+        const int g0 = p * (NG / P) + w * gpw;
+        int32_t *wkey = sh.key + w * MP_SW;
+        double *wval = sh.val + w * MP_SW;
+        const int keys_w = slice_accumulate<MP_SW, MODE, 8>(a, j, g0, g0 + gpw, wkey, wval, &sh.wovf[w],
+                                                            MP_CAPW, &sh.dmisc[3]);
+        if (lane() == 0) {
+            sh.wcnt[w] = keys_w;
+            if (keys_w > MP_CAPW) sh.wovf[w] = 1;
+        }
+        __syncthreads();
+        int mp = 0, ovf = 0, pre = 0;
+        for (int q = 0; q < MP_NW; ++q) {
+            if (q < w) pre += sh.wcnt[q];
+            mp += sh.wcnt[q];
+            ovf |= sh.wovf[q];
+        }
+        if (ovf || off + mp > capv) {
+            if (tid == 0) a.out_cnt[j] = -1;
+            return;
+        }
+        // append this wave's keys (slot order) after the earlier waves and passes
+        int run = 0;
+        for (int s0 = 0; s0 < MP_SW; s0 += WAVE) {
+            const int k = wkey[s0 + lane()];
+            const uint64_t mk = ballot(k != EMPTY_KEY);
+            if (k != EMPTY_KEY) {
+                const int64_t d = base + off + pre + run + popc_below(mk);
+                a.out_row[d] = k;
+                if (MODE != MODE_COUNT) a.out_val[d] = wval[s0 + lane()];
+            }
+            run += __popcll(mk);
+        }
+        off += mp;
+        __syncthreads();  // the next pass clears the tables
+    }
+    if (tid == 0) a.out_cnt[j] = off;
+}
+
+// Finishing pass for the multi-pass columns: copies the m appended entries
+// to HBM scratch, sorts them by row, then writes them (expand) or runs the
+// fused epilogue on them (iterate).  Persistent workgroups with one scratch
+// slab each, like the HBM-table kernel.
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab, size_t slab_bytes)
+{
+    constexpr int NT = 1024;
+    constexpr int SM = (int)MP_MAX;
+    constexpr int NB = SM / 4;
+    constexpr int NBLK = SM / WAVE + 2;
+    __shared__ int32_t hist[256];
+    __shared__ int32_t misc[16];
+    __shared__ double dmisc[4];
+    __shared__ int32_t wsum[NT / WAVE];
+    char *my = slab + (size_t)blockIdx.x * slab_bytes;
+    int32_t *skey = (int32_t *)my;
+    double *sval = (double *)(my + (size_t)SM * 4);
+    int32_t *list = (int32_t *)(my + (size_t)SM * 12);
+    int32_t *sorted = list + SM;
+    int32_t *bcnt = sorted + SM;
+    int32_t *bcur = bcnt + NB;
+    int32_t *ip = bcur + NB;
+    double *p0 = (double *)(ip + NBLK + (NBLK & 1));
+    double *p1 = p0 + NBLK;
+    Scratch<int32_t> sc{skey, sval, list, sorted, bcnt, bcur, p0, p1, ip, hist, misc, dmisc, wsum};
+    const int tid = threadIdx.x;
+    for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
+        const int64_t j = a.cols[idx];
+        if (!multipass_column(a, j) || a.out_cnt[j] < 0) continue;
+        const int m = (int)a.out_cnt[j];
+        const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+        for (int q = tid; q < m; q += NT) {
+            skey[q] = a.out_row[base + q];
+            sval[q] = a.out_val[base + q];
+        }
+        __syncthreads();
+        const int32_t lo = a.lo[j];
+        const int64_t span = (int64_t)a.hi[j] - lo + 1;
+        if (MODE == MODE_EXPAND) {
+            sort_table<NT, true, int32_t>(skey, m, m, lo, span, bcnt, bcur, NB, list, wsum, [&](int rank, int s) {
+                a.out_row[base + rank] = skey[s];
+                a.out_val[base + rank] = sval[s];
+            });
+        } else {
+            sort_table<NT, true, int32_t>(skey, m, m, lo, span, bcnt, bcur, NB, list, wsum,
+                                          [&](int rank, int s) { sorted[rank] = s; });
+            __syncthreads();
+            const int64_t bs = a.B.colptr[j];
+            const int mj = (int)(a.B.colptr[j + 1] - bs);
+            iterate_epilogue<NT, true, int32_t>(a, j, m, bs, mj, base, skey, sval, sc, [&](int32_t k) {
+                int l = 0, h = m;  // first rank with key >= k
+                while (l < h) {
+                    const int mid = (l + h) >> 1;
+                    if (skey[sorted[mid]] < k) l = mid + 1;
+                    else h = mid;
+                }
+                return (l < m && skey[sorted[l]] == k) ? sorted[l] : -1;
+            });
+        }
+        __syncthreads();
+    }
+}
+
+size_t mpass_slab_bytes()
+{
+    const size_t SM = (size_t)MP_MAX, NB = SM / 4, NBLK = SM / WAVE + 2;
+    return ((SM * 20 + NB * 8 + (NBLK + (NBLK & 1)) * 4 + NBLK * 16) + 255) & ~(size_t)255;
+}
+
+void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
+                          hipStream_t st)
+{
+    if (a.ncols <= 0 || !a.goff || a.parts || mode == MODE_COUNT) return;
+    const int grid = std::min(nslabs, a.ncols);
+    if (mode == MODE_EXPAND) {
+        hipLaunchKernelGGL(k_numeric_mpass<MODE_EXPAND>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_finish_mpass<MODE_EXPAND>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
+                           slab_bytes);
+    } else {
+        hipLaunchKernelGGL(k_numeric_mpass<MODE_ITERATE>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_finish_mpass<MODE_ITERATE>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
+                           slab_bytes);
+    }
 }
 
 // Launch shapes per bin: (slots, waves per column, columns per workgroup,
@@ -1583,7 +1765,10 @@ __global__ __launch_bounds__(1024) void k_numeric_global(NumericArgs a, int S, i
     const int NB = (S / 4 < 64) ? 64 : S / 4;
     const int logS = __builtin_ctz((unsigned)S);
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
-        column_body<NT, MODE, 1, 2, int32_t, IS_MERGE, true>(a, a.cols[idx], S, logS, cap, NB, sc);
+        const int64_t j = a.cols[idx];
+        // columns of the multi-pass LDS kernel are done there (not in count mode)
+        if (!IS_MERGE && MODE != MODE_COUNT && multipass_column(a, j)) continue;
+        column_body<NT, MODE, 1, 2, int32_t, IS_MERGE, true>(a, j, S, logS, cap, NB, sc);
         __syncthreads();
     }
 }

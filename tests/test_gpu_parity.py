@@ -355,3 +355,31 @@ def test_phased_batched_iterate_is_identical(mcl):
     assert st["n_phases"] > 1
     assert torch.equal(X.colptr, ref.colptr) and torch.equal(X.rowidx, ref.rowidx)
     assert torch.equal(X.val, ref.val) and np.array_equal(c0, c1)
+
+
+def _huge_cluster_graph():
+    # clusters of ~4,200, ~8,300 and ~11,500 vertices, no inter-cluster edges:
+    # product columns of up to ~11,500 rows, beyond the largest LDS table set
+    return oracle.normalize(planted_graph(24000, 3, s_cap=13000, p_in=0.03, x=0.0, seed=61))
+
+
+def test_multipass_columns_iterate_parity(mcl):
+    A = _huge_cluster_graph()
+    _, _, st = check_iterate(mcl, A)
+    assert st["bin_cols"][7] > 0
+
+
+def test_multipass_columns_expand_and_exact_path(mcl):
+    A = _huge_cluster_graph()
+    C, flops, nnz = oracle.expand(A, A)
+    dA = up(mcl, A)
+    G, st = mcl.expand(dA, dA)
+    assert st["bin_cols"][7] > 0
+    assert_same_matrix(G.to_host(), C, exact=True)
+    # underestimated sizes: overflow, exact count, HBM tables -- same result
+    X, st2 = mcl.expand(dA, dA, est_scale=0.5)
+    assert st2["n_overflow"] > 0
+    assert torch.equal(X.rowidx, G.rowidx) and torch.equal(X.val, G.val)
+    ref, _, _ = mcl.iterate(dA)
+    Y, _, st3 = mcl.iterate(dA, est_scale=0.5)
+    assert torch.equal(Y.rowidx, ref.rowidx) and torch.equal(Y.val, ref.val)
