@@ -441,7 +441,8 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         int32_t *counts_d = dev_i + 1;       // 8 counters
         int32_t *nexact_d = dev_i + 9;
         int32_t *exact = mem.ws<int32_t>(novf);
-        mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d, mem.st);
+        mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d,
+                         mode != mcl::MODE_COUNT && a.goff && !a.parts, mem.st);
         int32_t hc[9];
         HIPC(hipMemcpyAsync(hc, counts_d, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
         HIPC(hipStreamSynchronize(mem.st));

@@ -87,7 +87,7 @@ void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, con
 void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,
                       int region, hipStream_t st);
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, hipStream_t st);
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, hipStream_t st);
 void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
                      const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
                      hipStream_t st);

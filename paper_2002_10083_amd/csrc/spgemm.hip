@@ -37,6 +37,14 @@ constexpr int64_t REGION_MASK = ((int64_t)1 << 48) - 1;
 // (load factor 3/4; more keys flag the column as overflowed).
 __host__ __device__ constexpr int bin_slots_c(int b) { return 128 << b; }
 __host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4; }
+// Multi-pass kernel of the largest columns (bin 7): 16 waves with 512-slot
+// tables per pass, 2 or 4 passes.
+constexpr int MP_NW = 16, MP_SW = 512;
+constexpr int MP_CAPW = (13 * MP_SW) / 16;
+// keys a column may be planned with per pass (headroom for the uneven
+// spread of rows over the 16 waves)
+constexpr int64_t MP_PASS_PLAN = (int64_t)MP_NW * MP_CAPW * 4 / 5;
+constexpr int64_t MP_MAX = 4 * MP_PASS_PLAN;
 // Keys a column may be planned with in bin b: bins of 1024+ slots split the
 // column over waves with private tables, so they keep 1/8 headroom for an
 // uneven spread of rows over the waves.
@@ -493,17 +501,20 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
                                               int32_t *__restrict__ bin, int64_t *__restrict__ capv,
                                               int32_t *__restrict__ bin_count,
                                               int32_t *__restrict__ exact_list,
-                                              int32_t *__restrict__ n_exact)
+                                              int32_t *__restrict__ n_exact, int to_multipass)
 {
     for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool valid = i < n;
         const int j = valid ? list[i] : 0;
         const int b = valid ? bin[j] : 0;
-        const bool up = valid && b + 1 < NUM_LDS_BINS;
+        // LDS bins move one up; the largest LDS bin moves to the multi-pass
+        // kernel at its full capacity (when available); the rest go to the
+        // exact count
+        const bool up = valid && (b + 1 < NUM_LDS_BINS || (to_multipass && b + 1 == NUM_LDS_BINS));
         if (up) {
             bin[j] = b + 1;
-            capv[j] = bin_cap_c(b + 1);
+            capv[j] = (b + 1 < NUM_LDS_BINS) ? (int64_t)bin_cap_c(b + 1) : MP_MAX;
         }
         wave_reserve<NUM_LDS_BINS + 1>(bin_count, b + 1, up);
         const int pos = wave_reserve<1>(n_exact, 0, valid && !up);
@@ -512,12 +523,12 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
 }
 
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, hipStream_t st)
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, hipStream_t st)
 {
     if (n <= 0) return;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_bump, dim3(grid), dim3(256), 0, st, list, n, bin, capv, bin_count, exact_list,
-                       n_exact);
+                       n_exact, (int)to_multipass);
 }
 
 // Per-bin totals of the launched columns: flops, nnz(B_*j), output count.
@@ -618,6 +629,15 @@ __device__ __forceinline__ void table_add(double *acc, double x)
     } else {
         *acc = *acc + x;
     }
+}
+
+// acc += x as a fire-and-forget LDS atomic add (one correctly rounded add).
+// Only used on tables private to one wave, where lanes of one instruction
+// never share a slot and successive instructions apply in issue order.
+__device__ __forceinline__ void lds_atomic_add(double *acc, double x)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) double *)acc, x, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ int bucket_match(const keys4 kb, int32_t k)
@@ -1318,9 +1338,11 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 // table of SW slots (cleared here).  Returns the number of keys it placed;
 // *wovf is raised when a probe fails; more than capw keys stop the
 // accumulation early (the caller treats both as overflow).
+// col_keys / col_cap: a counter shared by the column's waves and the
+// column's key capacity; a wave stops as soon as the column total exceeds it.
 template <int SW, int MODE, int D>
 __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1, int32_t *wkey, double *wval,
-                                int *wovf, int capw, double *never)
+                                int *wovf, int capw, double *never, int *col_keys, int64_t col_cap)
 {
     constexpr int NBW = SW / 4;
     constexpr int LOGNBW = __builtin_ctz(NBW);
@@ -1337,6 +1359,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     const int mj = (int)(a.B.colptr[j + 1] - bs);
     bool overflow = false;
     int keys_w = 0;     // keys this wave placed
+    int published = 0;  // of which already added to *col_keys
     double sink = 0.0;  // sum of the products a lane saw (kept live, never used)
 
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
@@ -1353,50 +1376,99 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             ws = a.A.colptr[k] + r0;
             len = r1 - r0;
         }
-        const int nch = (len + WAVE - 1) / WAVE;
-        const int cpre = wave_incl_scan(nch) - nch;
-        const int total = readlane_i(cpre + nch, WAVE - 1);
-        // Burst groups of D chunks: loads issued back to back, first-bucket
-        // reads of all D chunks together, then insertion and the value
-        // updates chunk by chunk (in issue order).
-        for (int c0 = 0; c0 < total && !overflow; c0 += D) {
+        // The runs of the batch's steps are packed back to back: chunk c
+        // holds entries [64c, 64c + 64) of the concatenation, usually
+        // pieces of several steps.  pre = start of the lane's run.
+        const int pre = wave_incl_scan(len) - len;
+        const int total = readlane_i(pre + len, WAVE - 1);
+        const int nchunk = (total + WAVE - 1) / WAVE;
+        // Groups of D chunks: loads issued back to back, first-bucket reads
+        // of all D chunks together, then insertion, then the value updates
+        // chunk by chunk and, inside a chunk, step by step (atomic adds of
+        // one wave apply in issue order, so every row still sees its steps
+        // in ascending k).  Groups are double-buffered: the loads of group
+        // g+1 are in flight while group g is folded in.
+        struct Grp {
             int32_t rr[D];
             double vv[D], bb[D];
+            int sub[D], nsub[D];
+        };
+        auto issue = [&](Grp &G, int c0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                const int c = c0 + i;
-                const uint64_t mk = ballot(nch > 0 && cpre <= c);
-                const int u = (mk != 0) ? 63 - __clzll(mk) : 0;
-                const int ic = c - readlane_i(cpre, u);
-                const int64_t base = readlane_i64(ws, u) + (int64_t)ic * WAVE;
-                const int e = ic * WAVE + lane();
-                const bool in = (c < total) && e < readlane_i(len, u);
-                rr[i] = ldg(in ? a.A.rowidx + base + lane() : dummy_r);
-                if (MODE != MODE_COUNT) vv[i] = ldg(in ? a.A.val + base + lane() : dummy_v);
-                bb[i] = readlane_d(bv, u);
+                const int F = (c0 + i) * WAVE;
+                // step holding entry F, then the steps starting inside the chunk
+                const uint64_t m0 = ballot(len > 0 && pre <= F);
+                const int u0 = (m0 != 0) ? 63 - __clzll(m0) : 0;
+                int64_t my_ws = readlane_i64(ws, u0);
+                int my_pre = readlane_i(pre, u0);
+                double my_b = readlane_d(bv, u0);
+                int my_sub = 0, ns = 1;
+                uint64_t ms = ballot(len > 0 && pre > F && pre < F + WAVE);
+                while (ms) {
+                    const int l = __ffsll((long long)ms) - 1;
+                    ms &= ms - 1;
+                    const int pl = readlane_i(pre, l);
+                    const int64_t wl = readlane_i64(ws, l);
+                    const double bl = readlane_d(bv, l);
+                    if (F + lane() >= pl) {
+                        my_ws = wl;
+                        my_pre = pl;
+                        my_b = bl;
+                        my_sub = ns;
+                    }
+                    ++ns;
+                }
+                const bool in = F + lane() < total;
+                const int64_t ad = my_ws + (F + lane() - my_pre);
+                G.rr[i] = ldg(in ? a.A.rowidx + ad : dummy_r);
+                if (MODE != MODE_COUNT) G.vv[i] = ldg(in ? a.A.val + ad : dummy_v);
+                G.bb[i] = my_b;
+                G.sub[i] = my_sub;
+                G.nsub[i] = ns;
             }
+        };
+        auto fold = [&](Grp &G) {
             uint32_t hb[D];
             keys4 kb[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                hb[i] = sub_bucket(max(rr[i], 0), LOGNBW);
+                hb[i] = sub_bucket(max(G.rr[i], 0), LOGNBW);
                 kb[i] = load_bucket<true>(wkey, hb[i]);
             }
+            int sl[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                int sl = -1;
+                sl[i] = -1;
                 bool fresh = false;
-                if (rr[i] >= 0) sl = place_key<true>(wkey, rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
+                if (G.rr[i] >= 0) sl[i] = place_key<true>(wkey, G.rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
                 keys_w += __popcll(ballot(fresh));
-                if (MODE != MODE_COUNT) {
+            }
+            if (MODE != MODE_COUNT) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
                     // `sink` keeps the value load out of the branch
-                    const double prod = vv[i] * bb[i];
+                    const double prod = G.vv[i] * G.bb[i];
                     sink += prod;
-                    if (sl >= 0) table_add<true>(wval + sl, prod);
+                    for (int q = 0; q < G.nsub[i]; ++q)
+                        if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod);
                 }
             }
+            int tot = 0;
+            if (lane() == 0) tot = atomicAdd(col_keys, keys_w - published) + (keys_w - published);
+            tot = readlane_i(tot, 0);
+            published = keys_w;
             group_sync<WAVE>();
-            overflow = *wovf != 0 || keys_w > capw;
+            overflow = *wovf != 0 || keys_w > capw || tot > col_cap;
+        };
+        Grp GA, GB;
+        issue(GA, 0);
+        for (int c0 = 0; c0 < nchunk && !overflow; c0 += 2 * D) {
+            issue(GB, c0 + D);  // past the last chunk: masked loads of the dummy word
+            fold(GA);
+            if (c0 + D >= nchunk || overflow) break;
+            issue(GA, c0 + 2 * D);
+            fold(GB);
         }
     }
     if (MODE != MODE_COUNT && sink == -1.0) *never = sink;  // never: products are >= 0 or NaN
@@ -1433,8 +1505,11 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     const int64_t j = a.cols[blockIdx.x];
+    if (tid == 0) sh.misc[8] = 0;
+    __syncthreads();
+    const int64_t col_cap = a.capv ? min((int64_t)CAPT, a.capv[j]) : (int64_t)CAPT;
     const int keys_w = slice_accumulate<SW, MODE, D>(a, j, w * G, (w + 1) * G, sh.key + w * SW, sh.val + w * SW,
-                                                     &sh.wovf[w], CAPW, &sh.dmisc[3]);
+                                                     &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[8], col_cap);
     if (lane() == 0) {
         sh.wcnt[w] = keys_w;
         if (keys_w > CAPW) sh.wovf[w] = 1;
@@ -1488,12 +1563,6 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
 // appends its keys and values, unsorted, to the column's output slot; the
 // finishing kernel below sorts them and runs the epilogue.
 // ---------------------------------------------------------------------------
-constexpr int MP_NW = 16, MP_SW = 512;
-constexpr int MP_CAPW = (13 * MP_SW) / 16;
-// keys a column may be planned with per pass (headroom for the uneven
-// spread of rows over the 16 waves)
-constexpr int64_t MP_PASS_PLAN = (int64_t)MP_NW * MP_CAPW * 4 / 5;
-constexpr int64_t MP_MAX = 4 * MP_PASS_PLAN;
 
 __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j)
 {
@@ -1508,6 +1577,7 @@ __global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
         double val[STOT];
         int32_t key[STOT];
         int32_t wcnt[MP_NW], wovf[MP_NW];
+        int32_t total[4];
         double dmisc[4];
     };
     __shared__ Sh sh __attribute__((aligned(16)));
@@ -1524,8 +1594,10 @@ __global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
         const int g0 = p * (NG / P) + w * gpw;
         int32_t *wkey = sh.key + w * MP_SW;
         double *wval = sh.val + w * MP_SW;
-        const int keys_w = slice_accumulate<MP_SW, MODE, 8>(a, j, g0, g0 + gpw, wkey, wval, &sh.wovf[w],
-                                                            MP_CAPW, &sh.dmisc[3]);
+        if (tid == 0) sh.total[p & 1] = 0;
+        __syncthreads();
+        const int keys_w = slice_accumulate<MP_SW, MODE, 4>(a, j, g0, g0 + gpw, wkey, wval, &sh.wovf[w],
+                                                            MP_CAPW, &sh.dmisc[3], &sh.total[p & 1], capv - off);
         if (lane() == 0) {
             sh.wcnt[w] = keys_w;
             if (keys_w > MP_CAPW) sh.wovf[w] = 1;
@@ -1672,31 +1744,34 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 16: MCL_LAUNCH(512, 1, 4, 2, 4, false); break;
     case 17: MCL_LAUNCH(512, 1, 4, 2, 8, false); break;
     case 24: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
-    case 25: MCL_SPLIT(2, 8); break;
+    case 25: MCL_SPLIT(2, 4); break;
     case 26: MCL_LAUNCH(1024, 2, 1, 2, 4, true); break;
     case 27: MCL_LAUNCH(1024, 1, 2, 4, 4, false); break;
     case 32: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
-    case 33: MCL_SPLIT(4, 8); break;
+    case 33: MCL_SPLIT(4, 4); break;
     case 34: MCL_LAUNCH(2048, 4, 1, 2, 4, true); break;
     case 35: MCL_LAUNCH(2048, 4, 1, 1, 8, true); break;
     case 40: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
     case 41: MCL_SPLIT(8, 8); break;
     case 42: MCL_LAUNCH(4096, 8, 1, 1, 4, true); break;
-    case 43: MCL_LAUNCH(4096, 8, 1, 1, 8, true); break;
+    case 43: MCL_SPLIT(8, 4); break;
     case 44: MCL_LAUNCH(4096, 8, 1, 1, 8, false); break;
     case 48: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
-    case 49: MCL_SPLIT(16, 8); break;
+    case 49: MCL_SPLIT(16, 4); break;
     case 50: MCL_LAUNCH(8192, 16, 1, 1, 4, true); break;
     case 51: MCL_LAUNCH(8192, 16, 1, 1, 8, true); break;
     case 52: MCL_LAUNCH(8192, 16, 1, 1, 8, false); break;
-    case 53: MCL_LAUNCH(8192, 16, 1, 1, 16, false); break;
+    case 53: MCL_SPLIT(16, 2); break;
     default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
     }
 #undef MCL_SPLIT
 #undef MCL_LAUNCH
 }
 
-bool lds_variant_sliced(int bin, int variant) { return bin >= 3 && bin <= 6 && variant == 1; }
+bool lds_variant_sliced(int bin, int variant)
+{
+    return (bin >= 3 && bin <= 6 && variant == 1) || (bin == 5 && variant == 3) || (bin == 6 && variant == 5);
+}
 
 int lds_bin_variants(int bin)
 {
