@@ -320,8 +320,13 @@ def main():
     dom = int(np.argmax(mean_ms))
     byt = bin_bytes(sts[0], dom)
     achieved = byt / (mean_ms[dom] * 1e-3) / 1e9
-    name = ("k_numeric_lds<%d slots>" % (128 << dom)) if dom < 7 else "k_numeric_global"
     variant = (policy >> (4 * dom)) & 15 if dom < 7 else 0
+    if dom == 7:
+        name = "k_numeric_mpass + k_finish_mpass (multi-pass sliced tables)"
+    elif dom >= 3 and variant == 0:
+        name = "k_numeric_hsplit<%d waves, 512 slots each> (bin %d)" % (1 << (dom - 2), dom)
+    else:
+        name = "k_numeric_lds<%d slots> (bin %d, launch variant %d)" % (128 << dom, dom, variant)
     kernel_key = "bin%d-v%d-keys%d" % (dom, variant, keys)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel_key),

@@ -73,10 +73,6 @@ typedef struct {
     void *ctx;
 } mcl_allocator;
 
-/* mcl_params.schedule flags */
-#define MCL_SCHED_XCD 1      /* give each accelerator die (XCD, own L2) a contiguous run of a
-                                bin's column list instead of every 8th column */
-
 typedef struct {
     double prune_threshold;  /* theta: keep b >= theta (Alg. 1 prune) */
     int32_t select_num;      /* S: keep the S largest when more than S pass theta; 0 = off */
@@ -94,8 +90,6 @@ typedef struct {
     int32_t bin_policy;      /* launch shape per table bin, 4 bits per bin (0 = default) */
     float *est_out;          /* optional device float[ncols]: the estimate used per column */
     int64_t *nnz_out;        /* optional device int64[ncols]: exact nnz of each product column */
-    int32_t schedule;        /* work-order flags, MCL_SCHED_* (0 = plain order); never changes
-                                results, only the order in which columns are processed */
     int64_t phase_bytes;     /* mcl_iterate: bound on the product's temporary storage; when the
                                 planned temp exceeds it the columns are processed in phases of
                                 contiguous column ranges (same results).  0 = 40 % of the free

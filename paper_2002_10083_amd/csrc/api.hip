@@ -695,7 +695,6 @@ int mcl_expand(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, const mcl_params 
         a.A = dA;
         a.B = dB;
         a.pa = prune_args(p);
-        a.xcd_order = p.schedule & MCL_SCHED_XCD;
         use_sliced_source(mem, a, (uint32_t)p.bin_policy);
         EngineOut eo;
         engine(mem, n, A->nrows, mcl::MODE_EXPAND, a, pl, eo, tm, B->colptr, (uint32_t)p.bin_policy);
@@ -774,7 +773,6 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
         a.nnz_prod = nnzp;
         a.delta = delta;
         a.mode = mode;
-        a.xcd_order = p.schedule & MCL_SCHED_XCD;
         const uint32_t policy = (uint32_t)p.bin_policy;
         use_sliced_source(mem, a, policy);
         std::vector<int64_t> cut_base;

@@ -42,7 +42,6 @@ struct NumericArgs {
     const DevCSC *parts;      // merge mode: device array of nparts matrices (else null)
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
-    int32_t xcd_order;        // nonzero: contiguous runs of the column list per XCD
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
 };

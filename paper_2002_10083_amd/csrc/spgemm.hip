@@ -1209,21 +1209,6 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
 // ---------------------------------------------------------------------------
 // LDS-bin kernels
 // ---------------------------------------------------------------------------
-// Workgroup b of a launch runs on XCD b mod 8 (the dispatcher deals
-// workgroups round-robin over the eight dies, each with its own L2).  With
-// xcd_order set, XCD x takes the x-th contiguous eighth of the column list,
-// so neighbouring columns (which share source columns when the list is in a
-// locality order) meet in one L2.  A bijection on [0, n).
-constexpr uint32_t NUM_XCD = 8;
-
-__device__ __forceinline__ uint32_t sched_block(uint32_t b, uint32_t n, int xcd_order)
-{
-    if (!xcd_order) return b;
-    const uint32_t x = b % NUM_XCD, r = b / NUM_XCD;
-    const uint32_t q = n / NUM_XCD, rem = n % NUM_XCD;
-    return x * q + min(x, rem) + r;
-}
-
 template <int S>
 struct LdsBin {
     static constexpr int CAP = (3 * S) / 4;
@@ -1251,7 +1236,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
     };
     __shared__ Col cols[CPW] __attribute__((aligned(16)));
     const int ci = threadIdx.x / NT;
-    const int64_t idx = (int64_t)sched_block(blockIdx.x, gridDim.x, a.xcd_order) * CPW + ci;
+    const int64_t idx = (int64_t)blockIdx.x * CPW + ci;
     if (idx >= a.ncols) return;  // whole groups exit together
     Col &c = cols[ci];
     Scratch<uint16_t> sc{c.key, c.val, c.list, c.sorted, c.bcnt, c.bcur, c.p0, c.p1,
@@ -1360,6 +1345,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     bool overflow = false;
     int keys_w = 0;     // keys this wave placed
     int published = 0;  // of which already added to *col_keys
+    int col_total = 0;  // column total seen at the last publication
     double sink = 0.0;  // sum of the products a lane saw (kept live, never used)
 
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
@@ -1454,12 +1440,14 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                         if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod);
                 }
             }
-            int tot = 0;
-            if (lane() == 0) tot = atomicAdd(col_keys, keys_w - published) + (keys_w - published);
-            tot = readlane_i(tot, 0);
-            published = keys_w;
+            if (keys_w != published) {  // new keys: publish them, read the column total
+                int t = 0;
+                if (lane() == 0) t = atomicAdd(col_keys, keys_w - published) + (keys_w - published);
+                col_total = readlane_i(t, 0);
+                published = keys_w;
+            }
             group_sync<WAVE>();
-            overflow = *wovf != 0 || keys_w > capw || tot > col_cap;
+            overflow = *wovf != 0 || keys_w > capw || col_total > col_cap;
         };
         Grp GA, GB;
         issue(GA, 0);
@@ -1719,11 +1707,11 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
 
 // Launch shapes per bin: (slots, waves per column, columns per workgroup,
 // entries per lane per chunk, chunks per group, double-buffered groups), or
-// the sliced-table kernel (waves, chunks per group; variant 1 of bins 3-6,
-// which needs the sliced source layout).  Variant 0 is the
-// fastest shape measured on the 1M-vertex planted graph; the
-// others are alternatives the tuner may select through mcl_params.bin_policy
-// (4 bits per bin).  Merge and exact-count launches always use variant 0.
+// the sliced-table kernel (waves, chunks per group; reads the sliced source
+// layout).  Variant 0 is the fastest shape measured on the 1M-vertex planted
+// graph; the others are alternatives the tuner may select through
+// mcl_params.bin_policy (4 bits per bin).  Merge and exact-count launches use
+// the shared-table shape (shared_table_variant).
 template <int MODE, bool IS_MERGE>
 static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStream_t st)
 {
@@ -1732,7 +1720,6 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 #define MCL_LAUNCH(S_, NW_, CPW_, E_, D_, P_)                                               \
     hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE, P_>),          \
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
-    if (MODE == MODE_COUNT) variant = 0;
 #define MCL_SPLIT(NW_, D_)                                                                   \
     if constexpr (!IS_MERGE && MODE != MODE_COUNT)                                           \
         hipLaunchKernelGGL((k_numeric_hsplit<NW_, 512, MODE, D_>), dim3(n), dim3(NW_ * WAVE), 0, st, a)
@@ -1743,21 +1730,21 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 9: MCL_LAUNCH(256, 1, 4, 1, 8, false); break;
     case 16: MCL_LAUNCH(512, 1, 4, 2, 4, false); break;
     case 17: MCL_LAUNCH(512, 1, 4, 2, 8, false); break;
-    case 24: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
-    case 25: MCL_SPLIT(2, 4); break;
+    case 24: MCL_SPLIT(2, 4); break;
+    case 25: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
     case 26: MCL_LAUNCH(1024, 2, 1, 2, 4, true); break;
     case 27: MCL_LAUNCH(1024, 1, 2, 4, 4, false); break;
-    case 32: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
-    case 33: MCL_SPLIT(4, 4); break;
+    case 32: MCL_SPLIT(4, 4); break;
+    case 33: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
     case 34: MCL_LAUNCH(2048, 4, 1, 2, 4, true); break;
     case 35: MCL_LAUNCH(2048, 4, 1, 1, 8, true); break;
-    case 40: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
-    case 41: MCL_SPLIT(8, 8); break;
+    case 40: MCL_SPLIT(8, 4); break;
+    case 41: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
     case 42: MCL_LAUNCH(4096, 8, 1, 1, 4, true); break;
-    case 43: MCL_SPLIT(8, 4); break;
+    case 43: MCL_SPLIT(8, 8); break;
     case 44: MCL_LAUNCH(4096, 8, 1, 1, 8, false); break;
-    case 48: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
-    case 49: MCL_SPLIT(16, 4); break;
+    case 48: MCL_SPLIT(16, 4); break;
+    case 49: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
     case 50: MCL_LAUNCH(8192, 16, 1, 1, 4, true); break;
     case 51: MCL_LAUNCH(8192, 16, 1, 1, 8, true); break;
     case 52: MCL_LAUNCH(8192, 16, 1, 1, 8, false); break;
@@ -1770,8 +1757,12 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
 
 bool lds_variant_sliced(int bin, int variant)
 {
-    return (bin >= 3 && bin <= 6 && variant == 1) || (bin == 5 && variant == 3) || (bin == 6 && variant == 5);
+    return (bin >= 3 && bin <= 6 && variant == 0) || (bin == 5 && variant == 3) || (bin == 6 && variant == 5);
 }
+
+// Launch used by merges and exact counts (modes the sliced kernels do not
+// serve): the shared-table shape of the bin.
+static int shared_table_variant(int bin) { return (bin >= 3 && bin <= 6) ? 1 : 0; }
 
 int lds_bin_variants(int bin)
 {
@@ -1782,11 +1773,12 @@ int lds_bin_variants(int bin)
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st)
 {
     if (a.parts) {
-        launch_lds_mode<MODE_EXPAND, true>(bin, 0, a, st);
+        launch_lds_mode<MODE_EXPAND, true>(bin, shared_table_variant(bin), a, st);
         return;
     }
+    if (lds_variant_sliced(bin, variant) && !a.goff) variant = shared_table_variant(bin);
     switch (mode) {
-    case MODE_COUNT: launch_lds_mode<MODE_COUNT, false>(bin, 0, a, st); break;
+    case MODE_COUNT: launch_lds_mode<MODE_COUNT, false>(bin, shared_table_variant(bin), a, st); break;
     case MODE_EXPAND: launch_lds_mode<MODE_EXPAND, false>(bin, variant, a, st); break;
     case MODE_ITERATE: launch_lds_mode<MODE_ITERATE, false>(bin, variant, a, st); break;
     }

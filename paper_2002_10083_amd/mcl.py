@@ -60,7 +60,7 @@ class Params(ctypes.Structure):
                 ("iteration", ctypes.c_int32), ("est_scale", ctypes.c_double),
                 ("mlp_weights", ctypes.c_void_p), ("validate", ctypes.c_int32),
                 ("bin_policy", ctypes.c_int32), ("est_out", ctypes.c_void_p),
-                ("nnz_out", ctypes.c_void_p), ("schedule", ctypes.c_int32),
+                ("nnz_out", ctypes.c_void_p),
                 ("phase_bytes", ctypes.c_int64)]
 
 
