@@ -79,3 +79,16 @@ def test_batched_mcl_equals_component_loop(drv):
     # clusters of the batched result are the oracle's clusters of the same matrix
     lab = oracle.clusters(Af.to_host())
     assert len(lab) == A.ncols
+
+
+def test_summa_merge_large_columns(drv):
+    # merged columns of ~10,800 rows: beyond the largest LDS table (HBM tables)
+    drivers, mcl = drv
+    A = oracle.normalize(planted_graph(12000, 2, s_cap=11000, p_in=0.02, x=0.0, seed=64))
+    parts = _stage_partials(A, 4, drivers)
+    ref, _ = oracle.binary_merge(parts)
+    C, info = drivers.summa_merge(mcl.DeviceCSC.from_host(A), 4, "binary")
+    g = C.to_host()
+    assert np.array_equal(g.colptr, ref.colptr)
+    assert np.array_equal(g.rowidx, ref.rowidx)
+    assert np.array_equal(g.val, ref.val)
