@@ -84,6 +84,18 @@ __device__ __forceinline__ int wave_max_i(int v)
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 
+// Per-lane gathers from lane `src` (any lane index per lane).
+__device__ __forceinline__ int shfl_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int src)
+{
+    const int lo = shfl_i((int)(uint32_t)v, src), hi = shfl_i((int)(v >> 32), src);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double shfl_d(double v, int src)
+{
+    return __longlong_as_double(shfl_i64(__double_as_longlong(v), src));
+}
+
 __device__ __forceinline__ int popc_below(uint64_t mask)
 {
     return __popcll(mask & ((1ull << lane()) - 1ull));

@@ -1379,39 +1379,31 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             double vv[D], bb[D];
             int sub[D], nsub[D];
         };
+        // lane l's run as an offset into A: entry f of the packed sequence,
+        // f in [pre_l, pre_l + len_l), is A entry f + base_l
+        const int64_t basev = ws - pre;
         auto issue = [&](Grp &G, int c0) {
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
-                // step holding entry F, then the steps starting inside the chunk
-                const uint64_t m0 = ballot(len > 0 && pre <= F);
-                const int u0 = (m0 != 0) ? 63 - __clzll(m0) : 0;
-                int64_t my_ws = readlane_i64(ws, u0);
-                int my_pre = readlane_i(pre, u0);
-                double my_b = readlane_d(bv, u0);
-                int my_sub = 0, ns = 1;
-                uint64_t ms = ballot(len > 0 && pre > F && pre < F + WAVE);
-                while (ms) {
-                    const int l = __ffsll((long long)ms) - 1;
-                    ms &= ms - 1;
-                    const int pl = readlane_i(pre, l);
-                    const int64_t wl = readlane_i64(ws, l);
-                    const double bl = readlane_d(bv, l);
-                    if (F + lane() >= pl) {
-                        my_ws = wl;
-                        my_pre = pl;
-                        my_b = bl;
-                        my_sub = ns;
-                    }
-                    ++ns;
-                }
+                // runs are in lane order with ascending starts: lanes
+                // [0, cnt0) start at or before F, the next k lanes start
+                // inside the chunk; a lane's step is the last run starting at
+                // or before its entry
+                const int cnt0 = __popcll(ballot(pre <= F));
+                const int k = __popcll(ballot(pre > F && pre < F + WAVE));
+                int rank = 0;
+                for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
+                const int u = max(cnt0 - 1 + rank, 0);
+                const int64_t bu = shfl_i64(basev, u);
+                const double b_u = shfl_d(bv, u);
                 const bool in = F + lane() < total;
-                const int64_t ad = my_ws + (F + lane() - my_pre);
+                const int64_t ad = bu + F + lane();
                 G.rr[i] = ldg(in ? a.A.rowidx + ad : dummy_r);
                 if (MODE != MODE_COUNT) G.vv[i] = ldg(in ? a.A.val + ad : dummy_v);
-                G.bb[i] = my_b;
-                G.sub[i] = my_sub;
-                G.nsub[i] = ns;
+                G.bb[i] = b_u;
+                G.sub[i] = rank;   // position of the lane's step among the chunk's steps
+                G.nsub[i] = k + 1;
             }
         };
         auto fold = [&](Grp &G) {
