@@ -645,10 +645,15 @@ __device__ __forceinline__ int bucket_match(const keys4 kb, int32_t k)
     return (kb.x == k) ? 0 : (kb.y == k) ? 1 : (kb.z == k) ? 2 : (kb.w == k) ? 3 : -1;
 }
 
+// First free slot of the bucket, or -1 when it is full.  The slots of a
+// bucket are claimed in order (an insertion takes the first free one), so
+// the occupied slots form a prefix; a torn or stale view only makes the
+// compare-and-swap fail and the insertion look again.
 __device__ __forceinline__ int bucket_empty(const keys4 kb)
 {
-    return (kb.x == EMPTY_KEY) ? 0 : (kb.y == EMPTY_KEY) ? 1 : (kb.z == EMPTY_KEY) ? 2
-         : (kb.w == EMPTY_KEY) ? 3 : -1;
+    const int occ = (kb.x != EMPTY_KEY ? 1 : 0) + (kb.y != EMPTY_KEY ? 1 : 0) + (kb.z != EMPTY_KEY ? 1 : 0) +
+                    (kb.w != EMPTY_KEY ? 1 : 0);
+    return occ < 4 ? occ : -1;
 }
 
 // Read bucket b.  LDS tables use one 128-bit LDS read; tables in HBM (the
