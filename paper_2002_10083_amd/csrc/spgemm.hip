@@ -1272,48 +1272,35 @@ __device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >
 // home bucket inside a sub-table of 2^logNB buckets: the hash bits below the group bits
 __device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return (row_hash(r) << 6) >> (32 - logNB); }
 
-// One wave per column: group sizes, boundaries, then a stable scatter.
+// One wave per column: group sizes (LDS counters), boundaries, then a
+// scatter by LDS cursors.  The order of the entries inside a group is not
+// specified (every consumer treats a run as a set of distinct rows).
 __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restrict__ rowo,
                                                       double *__restrict__ valo, int32_t *__restrict__ goff)
 {
-    const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
-    if (k >= A.ncols) return;
+    __shared__ int32_t ctr[4][NG];
+    const int w = threadIdx.x / WAVE;
+    const int64_t k = (int64_t)blockIdx.x * 4 + w;
+    if (k >= A.ncols) return;  // whole wave
+    int32_t *c = ctr[w];
     const int64_t p0 = A.colptr[k];
     const int len = (int)(A.colptr[k + 1] - p0);
-    int cnt = 0;  // lane g: size of group g
-    for (int c = 0; c < len; c += WAVE) {
-        const int e = c + lane();
-        const int g = (e < len) ? row_group(A.rowidx[p0 + e]) : NG;
-        for (int q = 0; q < NG; ++q) {
-            const int n = __popcll(ballot(g == q));
-            if (lane() == q) cnt += n;
-        }
-    }
-    int cur = wave_incl_scan(cnt) - cnt;  // lane g: first position of group g
+    c[lane()] = 0;
+    group_sync<WAVE>();
+    for (int e = lane(); e < len; e += WAVE) atomicAdd(&c[row_group(A.rowidx[p0 + e])], 1);
+    group_sync<WAVE>();
+    const int cnt = c[lane()];
+    const int cur = wave_incl_scan(cnt) - cnt;  // lane g: first position of group g
     goff[k * (NG + 1) + lane()] = cur;
     if (lane() == 0) goff[k * (NG + 1) + NG] = len;
-    for (int c = 0; c < len; c += WAVE) {
-        const int e = c + lane();
-        const bool in = e < len;
-        const int32_t r = in ? A.rowidx[p0 + e] : 0;
-        const double v = in ? A.val[p0 + e] : 0.0;
-        const int g = in ? row_group(r) : NG;
-        uint64_t mine = 0;
-        int base = 0;
-        for (int q = 0; q < NG; ++q) {
-            const uint64_t bq = ballot(g == q);
-            const int cq = readlane_i(cur, q);
-            if (g == q) {
-                mine = bq;
-                base = cq;
-            }
-            if (lane() == q) cur += __popcll(bq);
-        }
-        if (in) {
-            const int64_t d = p0 + base + popc_below(mine);
-            rowo[d] = r;
-            valo[d] = v;
-        }
+    group_sync<WAVE>();
+    c[lane()] = cur;
+    group_sync<WAVE>();
+    for (int e = lane(); e < len; e += WAVE) {
+        const int32_t r = A.rowidx[p0 + e];
+        const int64_t d = p0 + atomicAdd(&c[row_group(r)], 1);
+        rowo[d] = r;
+        valo[d] = A.val[p0 + e];
     }
 }
 
