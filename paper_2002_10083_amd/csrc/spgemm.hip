@@ -1375,6 +1375,9 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         // f in [pre_l, pre_l + len_l), is A entry f + base_l
         const int64_t basev = ws - pre;
         auto issue = [&](Grp &G, int c0) {
+            // two sweeps: the lane permutes of all D chunks first (one wait
+            // for all of them), then the addresses and the loads
+            int64_t bu[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
@@ -1387,15 +1390,18 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 int rank = 0;
                 for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
                 const int u = max(cnt0 - 1 + rank, 0);
-                const int64_t bu = shfl_i64(basev, u);
-                const double b_u = shfl_d(bv, u);
-                const bool in = F + lane() < total;
-                const int64_t ad = bu + F + lane();
-                G.rr[i] = ldg(in ? a.A.rowidx + ad : dummy_r);
-                if (MODE != MODE_COUNT) G.vv[i] = ldg(in ? a.A.val + ad : dummy_v);
-                G.bb[i] = b_u;
+                bu[i] = shfl_i64(basev, u);
+                G.bb[i] = shfl_d(bv, u);
                 G.sub[i] = rank;   // position of the lane's step among the chunk's steps
                 G.nsub[i] = k + 1;
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int F = (c0 + i) * WAVE;
+                const bool in = F + lane() < total;
+                const int64_t ad = bu[i] + F + lane();
+                G.rr[i] = ldg(in ? a.A.rowidx + ad : dummy_r);
+                if (MODE != MODE_COUNT) G.vv[i] = ldg(in ? a.A.val + ad : dummy_v);
             }
         };
         auto fold = [&](Grp &G) {
