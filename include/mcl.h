@@ -38,7 +38,8 @@
  * Determinism: for the same input and parameters every entry point produces
  * bit-identical output, whatever the estimator, table sizes or batching.
  * Entries of a product column are accumulated in ascending order of the
- * inner index k as acc = fma(a_ik, b_kj, acc).
+ * inner index k as acc = acc + a_ik*b_kj, the product rounded to double
+ * before the addition (no fused multiply-add).
  */
 #ifndef MCL_H
 #define MCL_H

@@ -541,8 +541,8 @@ void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mc
     const float *colmin = nullptr;
     const int r = p.cohen_keys;
     if (p.estimator == MCL_EST_COHEN) {
-        float *keys = mem.ws<float>(A.nrows * r);
-        float *cm = mem.ws<float>(A.ncols * r);
+        float *keys = mem.ws<float>(A.nrows * mcl::cohen_stride(r));
+        float *cm = mem.ws<float>(A.ncols * mcl::cohen_stride(r));
         mcl::launch_cohen_keys(A.nrows, r, p.seed, p.iteration, keys, mem.st);
         mcl::launch_cohen_colmin(A, keys, r, cm, mem.st);
         colmin = cm;

@@ -64,9 +64,10 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
                      const float *ckeys, int r, float *est, float *feat, const int64_t *prev_nnz,
                      int iteration, hipStream_t st);
+// Cohen keys per row are stored with this stride (r rounded up to 4)
+inline int cohen_stride(int r) { return (r + 3) & ~3; }
 void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float *keys, hipStream_t st);
 void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st);
-void launch_cohen_finish(const DevCSC &B, const float *colmin, int r, float *est, hipStream_t st);
 // Chooses the bin of every column (bins 0..6 LDS, 7 = HBM table) and its capacity.
 void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const int32_t *hi,
                  const float *est, int est_kind, double est_scale, int64_t nrows,

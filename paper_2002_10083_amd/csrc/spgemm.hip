@@ -52,6 +52,33 @@ __host__ __device__ constexpr int plan_cap_c(int b) { return (b >= 3) ? (bin_cap
 int lds_bin_slots(int bin) { return bin_slots_c(bin); }
 int lds_bin_cap(int bin) { return bin_cap_c(bin); }
 
+// Per-lane minima of 16 key slots reduced over the 64 lanes with a
+// transposed butterfly: at each of the first four steps a lane keeps half of
+// its slots and receives the partner's values for them (8+4+2+1 exchanges),
+// then two plain steps finish.  Afterwards lane l holds the minimum of slot
+// cohen_slot(l) (the four lanes of a quad hold the same slot).
+__device__ __forceinline__ float keymin_reduce(float (&v)[16])
+{
+#pragma unroll
+    for (int h = 8, d = 32; h >= 1; h >>= 1, d >>= 1) {
+        const bool up = (lane() & d) != 0;
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const float send = up ? v[i] : v[i + h];
+            const float keep = up ? v[i + h] : v[i];
+            v[i] = fminf(keep, __shfl_xor(send, d, WAVE));
+        }
+    }
+    float x = v[0];
+    x = fminf(x, __shfl_xor(x, 2, WAVE));
+    x = fminf(x, __shfl_xor(x, 1, WAVE));
+    return x;
+}
+__device__ __forceinline__ int cohen_slot(int l)
+{
+    return ((l >> 5) & 1) * 8 + ((l >> 4) & 1) * 4 + ((l >> 3) & 1) * 2 + ((l >> 2) & 1);
+}
+
 // ---------------------------------------------------------------------------
 // symbolic pass: flops, row span, Cohen finish, MLP features
 // ---------------------------------------------------------------------------
@@ -59,6 +86,7 @@ int lds_bin_cap(int bin) { return bin_cap_c(bin); }
 // first and last row of A_*k.  Outputs flops_j, the row span [lo_j, hi_j] that
 // bounds the product column, and (optionally) Cohen's estimate from the
 // per-column key minima of A, and 12 MLP features.
+template <int RP>
 __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *__restrict__ flops,
                                                   int32_t *__restrict__ lo, int32_t *__restrict__ hi,
                                                   const float *__restrict__ colmin, int r,
@@ -68,7 +96,7 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
     const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
     if (j >= B.ncols) return;
     const int64_t bs = B.colptr[j], be = B.colptr[j + 1];
-    int64_t fl = 0, sq = 0, wlen = 0;
+    int64_t fl = 0, sq = 0;
     int mn = INT32_MAX, mx = -1, lmax = 0, lmin = INT32_MAX;
     double bmax = 0.0, bsq = 0.0, wl = 0.0;
     float cm[16];
@@ -91,9 +119,15 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
             mx = max(mx, A.rowidx[a1 - 1]);
         }
         if (colmin) {
+            const float4 *cr = (const float4 *)(colmin + (int64_t)k * RP);
 #pragma unroll
-            for (int l = 0; l < 16; ++l)
-                if (l < r) cm[l] = fminf(cm[l], colmin[(int64_t)k * r + l]);
+            for (int q = 0; q < RP / 4; ++q) {
+                const float4 x = cr[q];
+                cm[4 * q + 0] = fminf(cm[4 * q + 0], x.x);
+                cm[4 * q + 1] = fminf(cm[4 * q + 1], x.y);
+                cm[4 * q + 2] = fminf(cm[4 * q + 2], x.z);
+                cm[4 * q + 3] = fminf(cm[4 * q + 3], x.w);
+            }
         }
     }
     fl = wave_sum_i64(fl);
@@ -108,18 +142,19 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
     float esum = 0.f;
     bool reached = true;
     if (colmin) {
+        // column minima per key (slot cohen_slot(lane) on every lane), then
+        // the sum over the r keys, added in key order on lane 0
+        const float v = keymin_reduce(cm);
 #pragma unroll
         for (int l = 0; l < 16; ++l) {
             if (l < r) {
-                float v = cm[l];
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, WAVE));
-                if (!(v < INFINITY)) reached = false;
-                esum += v;
+                const float vl = __shfl(v, ((l >> 3) & 1) * 32 + ((l >> 2) & 1) * 16 + ((l >> 1) & 1) * 8 +
+                                               (l & 1) * 4, WAVE);
+                if (!(vl < INFINITY)) reached = false;
+                esum += vl;
             }
         }
     }
-    (void)wlen;
     if (lane() == 0) {
         flops[j] = fl;
         lo[j] = (mx >= 0) ? mn : 0;
@@ -151,9 +186,17 @@ void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *
                      int iteration, hipStream_t st)
 {
     if (B.ncols == 0) return;
-    const unsigned grid = (unsigned)((B.ncols + 3) / 4);
-    hipLaunchKernelGGL(k_symbolic, dim3(grid), dim3(256), 0, st, A, B, flops, lo, hi, colmin, r, est,
-                       feat, prev_nnz, iteration);
+    const dim3 grid((unsigned)((B.ncols + 3) / 4));
+#define MCL_SYM(RP_)                                                                                   \
+    hipLaunchKernelGGL(k_symbolic<RP_>, grid, dim3(256), 0, st, A, B, flops, lo, hi, colmin, r, est, feat, \
+                       prev_nnz, iteration)
+    switch (cohen_stride(r)) {
+    case 4: MCL_SYM(4); break;
+    case 8: MCL_SYM(8); break;
+    case 12: MCL_SYM(12); break;
+    default: MCL_SYM(16); break;
+    }
+#undef MCL_SYM
 }
 
 // Merge planning: for column j, ub_j = sum over parts of nnz (the exact-safe
@@ -208,16 +251,25 @@ __device__ __forceinline__ uint64_t sm64_out(uint64_t seed, uint64_t t)
     return sm64_mix(seed + (t + 1) * 0x9E3779B97F4A7C15ull);
 }
 
-__global__ __launch_bounds__(256) void k_cohen_keys(int64_t nrows, int r, uint64_t seed, int it,
+// Key l of row i is stored at keys[i*rp + l], rp = r rounded up to 4 (so a
+// row's keys are 16-byte aligned); its value depends only on (seed,
+// iteration, i*r + l).  Padding entries are +inf.
+__global__ __launch_bounds__(256) void k_cohen_keys(int64_t nrows, int r, int rp, uint64_t seed, int it,
                                                     float *__restrict__ keys)
 {
     const uint64_t s = sm64_out(seed, (uint64_t)it);
-    const int64_t n = nrows * r;
+    const int64_t n = nrows * rp;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t x = sm64_out(s, (uint64_t)q);
-        const double u = (double)((x >> 11) + 1ull) * (1.0 / 9007199254740992.0);
-        keys[q] = (float)(-log(u));
+        const int64_t i = q / rp;
+        const int l = (int)(q - i * rp);
+        float key = INFINITY;
+        if (l < r) {
+            const uint64_t x = sm64_out(s, (uint64_t)(i * r + l));
+            const double u = (double)((x >> 11) + 1ull) * (1.0 / 9007199254740992.0);
+            key = (float)(-log(u));
+        }
+        keys[q] = key;
     }
 }
 
@@ -225,10 +277,12 @@ void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float
                        hipStream_t st)
 {
     if (nrows == 0) return;
-    hipLaunchKernelGGL(k_cohen_keys, dim3(2048), dim3(256), 0, st, nrows, r, seed, iteration, keys);
+    hipLaunchKernelGGL(k_cohen_keys, dim3(2048), dim3(256), 0, st, nrows, r, cohen_stride(r), seed, iteration,
+                       keys);
 }
 
-// colmin[k*r + l] = min over rows i of A_*k of key(i, l).  One wave per column.
+// colmin[k*rp + l] = min over rows i of A_*k of key(i, l).  One wave per column.
+template <int RP>
 __global__ __launch_bounds__(256) void k_cohen_colmin(DevCSC A, const float *__restrict__ keys, int r,
                                                       float *__restrict__ colmin)
 {
@@ -238,30 +292,33 @@ __global__ __launch_bounds__(256) void k_cohen_colmin(DevCSC A, const float *__r
 #pragma unroll
     for (int l = 0; l < 16; ++l) cm[l] = INFINITY;
     for (int64_t p = A.colptr[k] + lane(); p < A.colptr[k + 1]; p += WAVE) {
-        const int64_t i = A.rowidx[p];
+        const float4 *kr = (const float4 *)(keys + (int64_t)A.rowidx[p] * RP);
 #pragma unroll
-        for (int l = 0; l < 16; ++l)
-            if (l < r) cm[l] = fminf(cm[l], keys[i * r + l]);
-    }
-#pragma unroll
-    for (int l = 0; l < 16; ++l) {
-        if (l < r) {
-            float v = cm[l];
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d, WAVE));
-            if (lane() == 0) colmin[k * r + l] = v;
+        for (int q = 0; q < RP / 4; ++q) {
+            const float4 x = kr[q];
+            cm[4 * q + 0] = fminf(cm[4 * q + 0], x.x);
+            cm[4 * q + 1] = fminf(cm[4 * q + 1], x.y);
+            cm[4 * q + 2] = fminf(cm[4 * q + 2], x.z);
+            cm[4 * q + 3] = fminf(cm[4 * q + 3], x.w);
         }
     }
+    const float v = keymin_reduce(cm);
+    const int slot = cohen_slot(lane());
+    if ((lane() & 3) == 0 && slot < RP) colmin[k * RP + slot] = (slot < r) ? v : INFINITY;
 }
 
 void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st)
 {
     if (A.ncols == 0) return;
-    hipLaunchKernelGGL(k_cohen_colmin, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A, keys,
-                       r, colmin);
+    const dim3 grid((unsigned)((A.ncols + 3) / 4));
+    switch (cohen_stride(r)) {
+    case 4: hipLaunchKernelGGL(k_cohen_colmin<4>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
+    case 8: hipLaunchKernelGGL(k_cohen_colmin<8>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
+    case 12: hipLaunchKernelGGL(k_cohen_colmin<12>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
+    default: hipLaunchKernelGGL(k_cohen_colmin<16>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
+    }
 }
 
-void launch_cohen_finish(const DevCSC &, const float *, int, float *, hipStream_t) {}
 
 // ---------------------------------------------------------------------------
 // planning: per column table size and bin
