@@ -43,11 +43,14 @@ struct NumericArgs {
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
+    int32_t src_end;          // sliced layout: index of the entry past the last (row -1, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
 };
 
 // ---- spgemm.hip
 constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced source layout
+// the sliced kernels address the sliced copy of A with 32-bit byte offsets
+constexpr int64_t SLICE_MAX_NNZ = (int64_t{1} << 29) - 1;
 constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin

@@ -1387,8 +1387,6 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     if (lane() == 0) *wovf = 0;
     group_sync<WAVE>();
 
-    const int32_t *dummy_r = (const int32_t *)a.dummy;
-    const double *dummy_v = (const double *)a.dummy;
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
     bool overflow = false;
@@ -1400,7 +1398,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
         // lane l: step tb + l -- start and length of this wave's run in A_*k, b
         const int t = tb + lane();
-        int64_t ws = 0;
+        int ws = 0;
         int len = 0;
         double bv = 0.0;
         if (t < mj) {
@@ -1408,7 +1406,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             bv = a.B.val[bs + t];
             const int32_t *go = a.goff + (int64_t)k * (NG + 1);
             const int r0 = go[g0], r1 = go[g1];
-            ws = a.A.colptr[k] + r0;
+            ws = (int)a.A.colptr[k] + r0;  // the sliced copy has fewer than 2^29 entries
             len = r1 - r0;
         }
         // The runs of the batch's steps are packed back to back: chunk c
@@ -1430,11 +1428,11 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         };
         // lane l's run as an offset into A: entry f of the packed sequence,
         // f in [pre_l, pre_l + len_l), is A entry f + base_l
-        const int64_t basev = ws - pre;
+        const int basev = ws - pre;
         auto issue = [&](Grp &G, int c0) {
             // two sweeps: the lane permutes of all D chunks first (one wait
             // for all of them), then the addresses and the loads
-            int64_t bu[D];
+            int bu[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
@@ -1447,7 +1445,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 int rank = 0;
                 for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
                 const int u = max(cnt0 - 1 + rank, 0);
-                bu[i] = shfl_i64(basev, u);
+                bu[i] = shfl_i(basev, u);
                 G.bb[i] = shfl_d(bv, u);
                 G.sub[i] = rank;   // position of the lane's step among the chunk's steps
                 G.nsub[i] = k + 1;
@@ -1455,10 +1453,10 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
-                const bool in = F + lane() < total;
-                const int64_t ad = bu[i] + F + lane();
-                G.rr[i] = ldg(in ? a.A.rowidx + ad : dummy_r);
-                if (MODE != MODE_COUNT) G.vv[i] = ldg(in ? a.A.val + ad : dummy_v);
+                // past the run ends: the sentinel entry (row -1, value 0)
+                const uint32_t ad = (F + lane() < total) ? (uint32_t)(bu[i] + F + lane()) : (uint32_t)a.src_end;
+                G.rr[i] = ldg_u32(a.A.rowidx, ad);
+                if (MODE != MODE_COUNT) G.vv[i] = ldg_u32(a.A.val, ad);
             }
         };
         auto fold = [&](Grp &G) {
@@ -1499,7 +1497,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         Grp GA, GB;
         issue(GA, 0);
         for (int c0 = 0; c0 < nchunk && !overflow; c0 += 2 * D) {
-            issue(GB, c0 + D);  // past the last chunk: masked loads of the dummy word
+            issue(GB, c0 + D);  // past the last chunk: loads of the sentinel entry
             fold(GA);
             if (c0 + D >= nchunk || overflow) break;
             issue(GA, c0 + 2 * D);
