@@ -43,7 +43,9 @@ struct NumericArgs {
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
-    int32_t src_end;          // sliced layout: index of the entry past the last (row -1, value 0)
+    const int32_t *shash;     // sliced copy of A (column ranges of A.colptr): row hashes
+    const double *sval;       //   and values
+    int32_t src_end;          // sliced copy: index of the entry past the last (hash 0xFFFFFFFF, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
 };
 
@@ -62,7 +64,7 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
                           hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
-// sliced copy of A (entries of each column ordered by row group) + boundaries
+// sliced copy of A: row hashes and values, each column ordered by row group, + group boundaries
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
 void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
                      const float *ckeys, int r, float *est, float *feat, const int64_t *prev_nnz,

@@ -1312,8 +1312,10 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 //
 // Rows are dealt to NG = 64 groups by the top six bits of their
 // multiplicative hash.  The sliced copy of a source matrix keeps every column
-// in place but orders its entries by group (rows ascending inside a group)
-// and records the 65 group boundaries of the column.  A workgroup of NW
+// in place but orders its entries by group (in no particular order inside a
+// group), stores each row as its hash (a bijection of 32-bit words, so the
+// tables key on it directly and the bucket bits need no multiply) and
+// records the 65 group boundaries of the column.  A workgroup of NW
 // waves then gives wave w the groups [w*G, (w+1)*G), G = NG/NW, with a
 // private table of SW slots: the entries of A_*k that wave w needs are one
 // contiguous, exactly known run, waves never share a row, so accumulation
@@ -1324,10 +1326,19 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 constexpr int NG = SLICE_GROUPS;
 static_assert(NG == WAVE, "one group per lane in the layout pass");
 
-__device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * 2654435761u; }
+// Row hash: multiplication by an odd constant, inverted by its inverse modulo
+// 2^32.  No row below 2^31 hashes to 0xFFFFFFFF (EMPTY_KEY): that word is the
+// hash of row -ROW_HASH_INV mod 2^32 = 0xF174D0AF.
+constexpr uint32_t ROW_HASH_MUL = 2654435761u;
+constexpr uint32_t ROW_HASH_INV = 0x0E8B2F51u;
+static_assert(ROW_HASH_MUL * ROW_HASH_INV == 1u, "inverse modulo 2^32");
+static_assert(0u - ROW_HASH_INV > 0x7FFFFFFFu, "no row < 2^31 hashes to EMPTY_KEY");
+__device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * ROW_HASH_MUL; }
+__device__ __forceinline__ int32_t row_of_hash(int32_t h) { return (int32_t)((uint32_t)h * ROW_HASH_INV); }
 __device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >> 26); }
 // home bucket inside a sub-table of 2^logNB buckets: the hash bits below the group bits
-__device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return (row_hash(r) << 6) >> (32 - logNB); }
+__device__ __forceinline__ uint32_t hash_bucket(uint32_t h, int logNB) { return (h << 6) >> (32 - logNB); }
+__device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return hash_bucket(row_hash(r), logNB); }
 
 // One wave per column: group sizes (LDS counters), boundaries, then a
 // scatter by LDS cursors.  The order of the entries inside a group is not
@@ -1354,9 +1365,9 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
     c[lane()] = cur;
     group_sync<WAVE>();
     for (int e = lane(); e < len; e += WAVE) {
-        const int32_t r = A.rowidx[p0 + e];
-        const int64_t d = p0 + atomicAdd(&c[row_group(r)], 1);
-        rowo[d] = r;
+        const uint32_t h = row_hash(A.rowidx[p0 + e]);
+        const int64_t d = p0 + atomicAdd(&c[h >> 26], 1);
+        rowo[d] = (int32_t)h;
         valo[d] = A.val[p0 + e];
     }
 }
@@ -1369,7 +1380,8 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 }
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
-// table of SW slots (cleared here).  Returns the number of keys it placed;
+// table of SW slots (cleared here), keyed by row hash.  Returns the number of
+// keys it placed;
 // *wovf is raised when a probe fails; more than capw keys stop the
 // accumulation early (the caller treats both as overflow).
 // col_keys / col_cap: a counter shared by the column's waves and the
@@ -1455,8 +1467,8 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 const int F = (c0 + i) * WAVE;
                 // past the run ends: the sentinel entry (row -1, value 0)
                 const uint32_t ad = (F + lane() < total) ? (uint32_t)(bu[i] + F + lane()) : (uint32_t)a.src_end;
-                G.rr[i] = ldg_u32(a.A.rowidx, ad);
-                if (MODE != MODE_COUNT) G.vv[i] = ldg_u32(a.A.val, ad);
+                G.rr[i] = ldg_u32(a.shash, ad);
+                if (MODE != MODE_COUNT) G.vv[i] = ldg_u32(a.sval, ad);
             }
         };
         auto fold = [&](Grp &G) {
@@ -1464,7 +1476,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             keys4 kb[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                hb[i] = sub_bucket(max(G.rr[i], 0), LOGNBW);
+                hb[i] = hash_bucket((uint32_t)G.rr[i], LOGNBW);
                 kb[i] = load_bucket<true>(wkey, hb[i]);
             }
             int sl[D];
@@ -1472,7 +1484,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             for (int i = 0; i < D; ++i) {
                 sl[i] = -1;
                 bool fresh = false;
-                if (G.rr[i] >= 0) sl[i] = place_key<true>(wkey, G.rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
+                if (G.rr[i] != EMPTY_KEY) sl[i] = place_key<true>(wkey, G.rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
                 keys_w += __popcll(ballot(fresh));
             }
             if (MODE != MODE_COUNT) {
@@ -1563,6 +1575,12 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
+    // keys back from hashes to rows, in place (slot positions stay those of the hash)
+    for (int s = tid; s < STOT; s += NT) {
+        const int32_t h = sh.key[s];
+        if (h != EMPTY_KEY) sh.key[s] = row_of_hash(h);
+    }
+    __syncthreads();
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
     const int32_t lo = a.lo[j];
@@ -1653,7 +1671,7 @@ __global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
             const uint64_t mk = ballot(k != EMPTY_KEY);
             if (k != EMPTY_KEY) {
                 const int64_t d = base + off + pre + run + popc_below(mk);
-                a.out_row[d] = k;
+                a.out_row[d] = row_of_hash(k);
                 if (MODE != MODE_COUNT) a.out_val[d] = wval[s0 + lane()];
             }
             run += __popcll(mk);
