@@ -1381,11 +1381,12 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
 // table of SW slots (cleared here), keyed by row hash.  Returns the number of
-// keys it placed;
-// *wovf is raised when a probe fails; more than capw keys stop the
-// accumulation early (the caller treats both as overflow).
+// keys it placed; *wovf is raised when a probe fails; more than capw keys
+// stop the accumulation early (the caller treats both as overflow).
 // col_keys / col_cap: a counter shared by the column's waves and the
-// column's key capacity; a wave stops as soon as the column total exceeds it.
+// column's key capacity; a wave stops soon after the column total exceeds it
+// (the total is read with the next group's bucket reads, so no LDS round
+// trip waits on it).
 template <int SW, int MODE, int D>
 __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1, int32_t *wkey, double *wval,
                                 int *wovf, int capw, double *never, int *col_keys, int64_t col_cap)
@@ -1396,7 +1397,6 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         wkey[s] = EMPTY_KEY;
         if (MODE != MODE_COUNT) wval[s] = 0.0;
     }
-    if (lane() == 0) *wovf = 0;
     group_sync<WAVE>();
 
     const int64_t bs = a.B.colptr[j];
@@ -1404,8 +1404,8 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     bool overflow = false;
     int keys_w = 0;     // keys this wave placed
     int published = 0;  // of which already added to *col_keys
-    int col_total = 0;  // column total seen at the last publication
-    double sink = 0.0;  // sum of the products a lane saw (kept live, never used)
+    int lovf = 0;       // a probe of this lane failed
+    int sinkh = 0;      // high words of the products a lane saw (kept live, never used)
 
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
         // lane l: step tb + l -- start and length of this wave's run in A_*k, b
@@ -1449,23 +1449,23 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
                 // runs are in lane order with ascending starts: lanes
-                // [0, cnt0) start at or before F, the next k lanes start
-                // inside the chunk; a lane's step is the last run starting at
-                // or before its entry
+                // [0, cnt0) start at or before F (cnt0 >= 1: lane 0 starts
+                // at 0), the next k lanes start inside the chunk; a lane's
+                // step is the last run starting at or before its entry
                 const int cnt0 = __popcll(ballot(pre <= F));
                 const int k = __popcll(ballot(pre > F && pre < F + WAVE));
                 int rank = 0;
                 for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
-                const int u = max(cnt0 - 1 + rank, 0);
+                const int u = cnt0 - 1 + rank;
                 bu[i] = shfl_i(basev, u);
-                G.bb[i] = shfl_d(bv, u);
-                G.sub[i] = rank;   // position of the lane's step among the chunk's steps
+                if (MODE != MODE_COUNT) G.bb[i] = shfl_d(bv, u);
+                G.sub[i] = rank;  // position of the lane's step among the chunk's steps
                 G.nsub[i] = k + 1;
             }
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
-                // past the run ends: the sentinel entry (row -1, value 0)
+                // past the run ends: the sentinel entry (hash 0xFFFFFFFF, value 0)
                 const uint32_t ad = (F + lane() < total) ? (uint32_t)(bu[i] + F + lane()) : (uint32_t)a.src_end;
                 G.rr[i] = ldg_u32(a.shash, ad);
                 if (MODE != MODE_COUNT) G.vv[i] = ldg_u32(a.sval, ad);
@@ -1479,32 +1479,41 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 hb[i] = hash_bucket((uint32_t)G.rr[i], LOGNBW);
                 kb[i] = load_bucket<true>(wkey, hb[i]);
             }
+            const int col_total = __hip_atomic_load((__attribute__((address_space(3))) int *)col_keys,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             int sl[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 sl[i] = -1;
                 bool fresh = false;
-                if (G.rr[i] != EMPTY_KEY) sl[i] = place_key<true>(wkey, G.rr[i], hb[i], kb[i], NBW - 1, wovf, fresh);
+                if (G.rr[i] != EMPTY_KEY) sl[i] = place_key<true>(wkey, G.rr[i], hb[i], kb[i], NBW - 1, &lovf, fresh);
                 keys_w += __popcll(ballot(fresh));
             }
-            if (MODE != MODE_COUNT) {
+            // a column already over its capacity is recomputed elsewhere: skip
+            // its value updates.  (Testing the total here, before any atomic,
+            // keeps the wait for it -- and for the permutes issued before
+            // it -- ahead of the atomics.)
+            const bool col_over = col_total > col_cap;
+            if (MODE != MODE_COUNT && !col_over) {
+                double prod[D];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    // `sink` keeps the value load out of the branch
-                    const double prod = G.vv[i] * G.bb[i];
-                    sink += prod;
-                    for (int q = 0; q < G.nsub[i]; ++q)
-                        if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod);
+                    prod[i] = G.vv[i] * G.bb[i];
+                    sinkh |= __double2hiint(prod[i]);  // keeps the value load out of the branch
                 }
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+                    for (int q = 0; q < G.nsub[i]; ++q)
+                        if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod[i]);
             }
-            if (keys_w != published) {  // new keys: publish them, read the column total
-                int t = 0;
-                if (lane() == 0) t = atomicAdd(col_keys, keys_w - published) + (keys_w - published);
-                col_total = readlane_i(t, 0);
+            const int delta = __builtin_amdgcn_readfirstlane(keys_w - published);
+            if (delta != 0) {  // new keys: publish them (no return value to wait for)
+                if (lane() == 0)
+                    __hip_atomic_fetch_add((__attribute__((address_space(3))) int *)col_keys, delta,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 published = keys_w;
             }
-            group_sync<WAVE>();
-            overflow = *wovf != 0 || keys_w > capw || col_total > col_cap;
+            overflow = ballot(lovf != 0) != 0 || keys_w > capw || col_over;
         };
         Grp GA, GB;
         issue(GA, 0);
@@ -1516,7 +1525,10 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             fold(GB);
         }
     }
-    if (MODE != MODE_COUNT && sink == -1.0) *never = sink;  // never: products are >= 0 or NaN
+    const bool any_ovf = ballot(lovf != 0) != 0;
+    if (lane() == 0) *wovf = any_ovf ? 1 : 0;
+    if (MODE != MODE_COUNT && sinkh < 0) *never = 1.0;  // never: products are >= 0
+    group_sync<WAVE>();
     return keys_w;
 }
 
