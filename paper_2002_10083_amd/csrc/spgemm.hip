@@ -1407,20 +1407,38 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     int lovf = 0;       // a probe of this lane failed
     int sinkh = 0;      // high words of the products a lane saw (kept live, never used)
 
-    for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
-        // lane l: step tb + l -- start and length of this wave's run in A_*k, b
+    // Step metadata of a batch of 64 steps (lane l: step tb + l): the row k
+    // and value of b, then this wave's run in A_*k (start, length).  The next
+    // batch's metadata is loaded while the current batch is folded in: its
+    // step rows at the batch start, its runs after the first group.
+    auto step_of = [&](int tb, int &k, double &b) {
         const int t = tb + lane();
-        int ws = 0;
-        int len = 0;
-        double bv = 0.0;
+        k = -1;
+        b = 0.0;
         if (t < mj) {
-            const int k = a.B.rowidx[bs + t];
-            bv = a.B.val[bs + t];
+            k = a.B.rowidx[bs + t];
+            b = a.B.val[bs + t];
+        }
+    };
+    auto run_of = [&](int k, int &ws, int &len) {
+        ws = 0;
+        len = 0;
+        if (k >= 0) {
             const int32_t *go = a.goff + (int64_t)k * (NG + 1);
             const int r0 = go[g0], r1 = go[g1];
             ws = (int)a.A.colptr[k] + r0;  // the sliced copy has fewer than 2^29 entries
             len = r1 - r0;
         }
+    };
+    int kn, wsn, lenn;
+    double bvn;
+    step_of(0, kn, bvn);
+    run_of(kn, wsn, lenn);
+    for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
+        const int ws = wsn, len = lenn;
+        const double bv = bvn;
+        bool next_runs = tb + WAVE < mj;  // the next batch's runs are still to be loaded
+        if (next_runs) step_of(tb + WAVE, kn, bvn);
         // The runs of the batch's steps are packed back to back: chunk c
         // holds entries [64c, 64c + 64) of the concatenation, usually
         // pieces of several steps.  pre = start of the lane's run.
@@ -1520,10 +1538,15 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         for (int c0 = 0; c0 < nchunk && !overflow; c0 += 2 * D) {
             issue(GB, c0 + D);  // past the last chunk: loads of the sentinel entry
             fold(GA);
+            if (next_runs) {
+                run_of(kn, wsn, lenn);
+                next_runs = false;
+            }
             if (c0 + D >= nchunk || overflow) break;
             issue(GA, c0 + 2 * D);
             fold(GB);
         }
+        if (next_runs) run_of(kn, wsn, lenn);
     }
     const bool any_ovf = ballot(lovf != 0) != 0;
     if (lane() == 0) *wovf = any_ovf ? 1 : 0;
