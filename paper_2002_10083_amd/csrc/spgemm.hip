@@ -816,9 +816,12 @@ __device__ __forceinline__ int bucket_of(int32_t k, int32_t lo, uint64_t mul, in
 
 // Exact k-th largest (kth >= 1) of m positive doubles get(p), p < m, by an
 // MSD radix select over their IEEE bit patterns (monotone for positive
-// values), 8 bits per pass.  Called by all NT threads of the group.
+// values), 8 bits per pass.  Once at most 64 values share the selected
+// prefix, they are gathered and one wave ranks them by comparison.  Called by
+// all NT threads of the group; hist holds 256 ints (reused for the gathered
+// values).
 template <int NT, bool GS, typename Get>
-__device__ double radix_kth_largest(Get get, int m, int kth, int *hist, int *misc)
+__device__ double radix_kth_largest(Get get, int m, int kth, int *hist, int *misc, double *dmisc)
 {
     const int tid = threadIdx.x % NT;
     const bool w0 = tid < WAVE;
@@ -846,23 +849,54 @@ __device__ double radix_kth_largest(Get get, int m, int kth, int *hist, int *mis
             int above = __shfl_down(x, 1, WAVE);
             if (l == WAVE - 1) above = 0;
             if (above < kk && kk <= x) {
-                int dsel = 4 * l, knew = kk;
+                int dsel = 4 * l, knew = kk, csel = 0;
                 const int cs[4] = {c3, c2, c1, c0};
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (above + cs[q] >= kk) { dsel = 4 * l + 3 - q; knew = kk - above; break; }
+                    if (above + cs[q] >= kk) { dsel = 4 * l + 3 - q; knew = kk - above; csel = cs[q]; break; }
                     above += cs[q];
                 }
                 misc[4] = dsel;
                 misc[5] = knew;
+                misc[12] = csel;  // values sharing the new prefix
+                misc[13] = 0;
             }
         }
         group_sync<NT, GS>();
         const int d = misc[4];
         kk = misc[5];
+        const int cand = misc[12];
         prefix |= (uint64_t)d << shift;
         pmask |= 255ull << shift;
         group_sync<NT, GS>();
+        if (cand <= WAVE && shift > 0) {
+            // gather the candidates' bit patterns (low words in hist[0, 64),
+            // high words in hist[64, 128)), then the kk-th largest of them
+            for (int p = tid; p < m; p += NT) {
+                const uint64_t u = (uint64_t)__double_as_longlong(get(p));
+                if ((u & pmask) == prefix) {
+                    const int q = atomicAdd(&misc[13], 1);
+                    hist[q] = (int)(uint32_t)u;
+                    hist[WAVE + q] = (int)(uint32_t)(u >> 32);
+                }
+            }
+            group_sync<NT, GS>();
+            if (w0 && lane() < cand) {
+                // positive doubles order like their bit patterns
+                const uint64_t v = ((uint64_t)(uint32_t)hist[WAVE + lane()] << 32) | (uint32_t)hist[lane()];
+                int gt = 0, ge = 0;
+                for (int q = 0; q < cand; ++q) {
+                    const uint64_t c = ((uint64_t)(uint32_t)hist[WAVE + q] << 32) | (uint32_t)hist[q];
+                    gt += (c > v) ? 1 : 0;
+                    ge += (c >= v) ? 1 : 0;
+                }
+                if (gt < kk && kk <= ge) dmisc[2] = __longlong_as_double((long long)v);  // ties write the same value
+            }
+            group_sync<NT, GS>();
+            const double r = dmisc[2];
+            group_sync<NT, GS>();
+            return r;
+        }
     }
     return __longlong_as_double((long long)prefix);
 }
@@ -912,7 +946,7 @@ __device__ void prune_decide(Get get, int m, const PruneArgs &pa, double *p0, do
     const int mode = misc[2], kth = misc[3];
     double t = dmisc[0];
     group_sync<NT, GS>();
-    if (kth > 0) t = radix_kth_largest<NT, GS>(get, m, kth, hist, misc);
+    if (kth > 0) t = radix_kth_largest<NT, GS>(get, m, kth, hist, misc, dmisc);
     *out_mode = mode;
     *out_t = t;
 }
