@@ -543,19 +543,21 @@ void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mc
     HIPC(hipMemsetAsync(pl.hbm_only, 0, n, mem.st));
     tm.mark();
     const size_t e0 = tm.ev.size() - 1;
-    const float *colmin = nullptr;
-    const int r = p.cohen_keys;
-    if (p.estimator == MCL_EST_COHEN) {
+    // column records of A (key minima with Cohen keys, row range and length)
+    const bool cohen = p.estimator == MCL_EST_COHEN;
+    const int r = cohen ? p.cohen_keys : 0;
+    float *rec = mem.ws<float>(std::max<int64_t>(A.ncols, 1) * mcl::col_rec_stride(r));
+    if (cohen) {
         float *keys = mem.ws<float>(A.nrows * mcl::cohen_stride(r));
-        float *cm = mem.ws<float>(A.ncols * mcl::cohen_stride(r));
         mcl::launch_cohen_keys(A.nrows, r, p.seed, p.iteration, keys, mem.st);
-        mcl::launch_cohen_colmin(A, keys, r, cm, mem.st);
-        colmin = cm;
+        mcl::launch_cohen_colmin(A, keys, r, rec, mem.st);
+    } else {
+        mcl::launch_col_records(A, rec, mem.st);
     }
     float *feat = feat_out;
     if (p.estimator == MCL_EST_MLP && !feat) feat = mem.ws<float>(n * 12);
-    mcl::launch_symbolic(A, B, pl.flops, pl.lo, pl.hi, colmin, r, colmin ? pl.est : nullptr, feat,
-                         nullptr, p.iteration, mem.st);
+    mcl::launch_symbolic(A, B, pl.flops, pl.lo, pl.hi, rec, r, cohen ? pl.est : nullptr, feat, nullptr,
+                         p.iteration, mem.st);
     tm.mark();
     const size_t e1 = tm.ev.size() - 1;
     if (p.estimator == MCL_EST_MLP) {

@@ -66,13 +66,20 @@ void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
 // sliced copy of A: row hashes and values, each column ordered by row group, + group boundaries
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
-void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
-                     const float *ckeys, int r, float *est, float *feat, const int64_t *prev_nnz,
-                     int iteration, hipStream_t st);
 // Cohen keys per row are stored with this stride (r rounded up to 4)
 inline int cohen_stride(int r) { return (r + 3) & ~3; }
+// Column records of A for the symbolic pass: RP key minima (RP = padded key
+// count, 0 without Cohen keys), then {first row, last row, length, 0} as
+// ints; the stride in floats keeps every record inside one 128-byte line.
+__host__ __device__ constexpr int col_rec_stride_c(int rp) { return rp == 0 ? 4 : rp == 4 ? 8 : rp <= 12 ? 16 : 32; }
+inline int col_rec_stride(int r) { return col_rec_stride_c(r > 0 ? cohen_stride(r) : 0); }
+// r = 0: records without key minima (launch_col_records), no Cohen estimate
+void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
+                     const float *rec, int r, float *est, float *feat, const int64_t *prev_nnz,
+                     int iteration, hipStream_t st);
 void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float *keys, hipStream_t st);
-void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st);
+void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *rec, hipStream_t st);
+void launch_col_records(const DevCSC &A, float *rec, hipStream_t st);
 // Chooses the bin of every column (bins 0..6 LDS, 7 = HBM table) and its capacity.
 void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const int32_t *hi,
                  const float *est, int est_kind, double est_scale, int64_t nrows,

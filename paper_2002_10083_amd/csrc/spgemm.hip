@@ -83,16 +83,18 @@ __device__ __forceinline__ int cohen_slot(int l)
 // symbolic pass: flops, row span, Cohen finish, MLP features
 // ---------------------------------------------------------------------------
 // One wavefront per column j of B.  For every nonzero b_kj: len = nnz(A_*k),
-// first and last row of A_*k.  Outputs flops_j, the row span [lo_j, hi_j] that
-// bounds the product column, and (optionally) Cohen's estimate from the
-// per-column key minima of A, and 12 MLP features.
+// first and last row of A_*k, read from the column record of k (RS floats:
+// RP key minima, then first row, last row, length).  Outputs flops_j, the
+// row span [lo_j, hi_j] that bounds the product column, and (RP > 0)
+// Cohen's estimate from the key minima, and 12 MLP features.
 template <int RP>
 __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *__restrict__ flops,
                                                   int32_t *__restrict__ lo, int32_t *__restrict__ hi,
-                                                  const float *__restrict__ colmin, int r,
+                                                  const float *__restrict__ rec, int r,
                                                   float *__restrict__ est, float *__restrict__ feat,
                                                   const int64_t *__restrict__ prev_nnz, int iteration)
 {
+    constexpr int RS = col_rec_stride_c(RP);
     const int64_t j = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
     if (j >= B.ncols) return;
     const int64_t bs = B.colptr[j], be = B.colptr[j + 1];
@@ -105,8 +107,9 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
     for (int64_t p = bs + lane(); p < be; p += WAVE) {
         const int k = B.rowidx[p];
         const double b = B.val[p];
-        const int64_t a0 = A.colptr[k], a1 = A.colptr[k + 1];
-        const int len = (int)(a1 - a0);
+        const float *rk = rec + (int64_t)k * RS;
+        const int4 info = *(const int4 *)(rk + RP);
+        const int len = info.z;
         fl += len;
         sq += (int64_t)len * len;
         lmax = max(lmax, len);
@@ -115,11 +118,11 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
         bsq += b * b;
         wl += b * (double)len;
         if (len > 0) {
-            mn = min(mn, A.rowidx[a0]);
-            mx = max(mx, A.rowidx[a1 - 1]);
+            mn = min(mn, info.x);
+            mx = max(mx, info.y);
         }
-        if (colmin) {
-            const float4 *cr = (const float4 *)(colmin + (int64_t)k * RP);
+        if constexpr (RP > 0) {
+            const float4 *cr = (const float4 *)rk;
 #pragma unroll
             for (int q = 0; q < RP / 4; ++q) {
                 const float4 x = cr[q];
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
     wl = wave_sum(wl);
     float esum = 0.f;
     bool reached = true;
-    if (colmin) {
+    if constexpr (RP > 0) {
         // column minima per key (slot cohen_slot(lane) on every lane), then
         // the sum over the r keys, added in key order on lane 0
         const float v = keymin_reduce(cm);
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
         flops[j] = fl;
         lo[j] = (mx >= 0) ? mn : 0;
         hi[j] = (mx >= 0) ? mx : 0;
-        if (colmin && est) est[j] = (reached && fl > 0) ? (float)(r - 1) / esum : 0.f;
+        if (RP > 0 && est) est[j] = (reached && fl > 0) ? (float)(r - 1) / esum : 0.f;
         if (feat) {
             const int m = (int)(be - bs);
             const double mean = m ? (double)fl / m : 0.0;
@@ -182,15 +185,16 @@ __global__ __launch_bounds__(256) void k_symbolic(DevCSC A, DevCSC B, int64_t *_
 }
 
 void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *lo, int32_t *hi,
-                     const float *colmin, int r, float *est, float *feat, const int64_t *prev_nnz,
+                     const float *rec, int r, float *est, float *feat, const int64_t *prev_nnz,
                      int iteration, hipStream_t st)
 {
     if (B.ncols == 0) return;
     const dim3 grid((unsigned)((B.ncols + 3) / 4));
 #define MCL_SYM(RP_)                                                                                   \
-    hipLaunchKernelGGL(k_symbolic<RP_>, grid, dim3(256), 0, st, A, B, flops, lo, hi, colmin, r, est, feat, \
+    hipLaunchKernelGGL(k_symbolic<RP_>, grid, dim3(256), 0, st, A, B, flops, lo, hi, rec, r, est, feat, \
                        prev_nnz, iteration)
-    switch (cohen_stride(r)) {
+    switch (r > 0 ? cohen_stride(r) : 0) {
+    case 0: MCL_SYM(0); break;
     case 4: MCL_SYM(4); break;
     case 8: MCL_SYM(8); break;
     case 12: MCL_SYM(12); break;
@@ -281,17 +285,25 @@ void launch_cohen_keys(int64_t nrows, int r, uint64_t seed, int iteration, float
                        keys);
 }
 
-// colmin[k*rp + l] = min over rows i of A_*k of key(i, l).  One wave per column.
+// Column record of A_*k (RS floats): rec[k*RS + l] = min over rows i of A_*k
+// of key(i, l) for l < RP (+inf past r), then first row, last row and
+// length of the column (as ints).  One wave per column.
 template <int RP>
 __global__ __launch_bounds__(256) void k_cohen_colmin(DevCSC A, const float *__restrict__ keys, int r,
-                                                      float *__restrict__ colmin)
+                                                      float *__restrict__ rec)
 {
+    constexpr int RS = col_rec_stride_c(RP);
     const int64_t k = (int64_t)blockIdx.x * 4 + threadIdx.x / WAVE;
     if (k >= A.ncols) return;
+    const int64_t a0 = A.colptr[k], a1 = A.colptr[k + 1];
+    if (lane() == 0) {
+        const int len = (int)(a1 - a0);
+        *(int4 *)(rec + k * RS + RP) = make_int4(len ? A.rowidx[a0] : 0, len ? A.rowidx[a1 - 1] : 0, len, 0);
+    }
     float cm[16];
 #pragma unroll
     for (int l = 0; l < 16; ++l) cm[l] = INFINITY;
-    for (int64_t p = A.colptr[k] + lane(); p < A.colptr[k + 1]; p += WAVE) {
+    for (int64_t p = a0 + lane(); p < a1; p += WAVE) {
         const float4 *kr = (const float4 *)(keys + (int64_t)A.rowidx[p] * RP);
 #pragma unroll
         for (int q = 0; q < RP / 4; ++q) {
@@ -304,19 +316,37 @@ __global__ __launch_bounds__(256) void k_cohen_colmin(DevCSC A, const float *__r
     }
     const float v = keymin_reduce(cm);
     const int slot = cohen_slot(lane());
-    if ((lane() & 3) == 0 && slot < RP) colmin[k * RP + slot] = (slot < r) ? v : INFINITY;
+    if ((lane() & 3) == 0 && slot < RP) rec[k * RS + slot] = (slot < r) ? v : INFINITY;
 }
 
-void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *colmin, hipStream_t st)
+void launch_cohen_colmin(const DevCSC &A, const float *keys, int r, float *rec, hipStream_t st)
 {
     if (A.ncols == 0) return;
     const dim3 grid((unsigned)((A.ncols + 3) / 4));
     switch (cohen_stride(r)) {
-    case 4: hipLaunchKernelGGL(k_cohen_colmin<4>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
-    case 8: hipLaunchKernelGGL(k_cohen_colmin<8>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
-    case 12: hipLaunchKernelGGL(k_cohen_colmin<12>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
-    default: hipLaunchKernelGGL(k_cohen_colmin<16>, grid, dim3(256), 0, st, A, keys, r, colmin); break;
+    case 4: hipLaunchKernelGGL(k_cohen_colmin<4>, grid, dim3(256), 0, st, A, keys, r, rec); break;
+    case 8: hipLaunchKernelGGL(k_cohen_colmin<8>, grid, dim3(256), 0, st, A, keys, r, rec); break;
+    case 12: hipLaunchKernelGGL(k_cohen_colmin<12>, grid, dim3(256), 0, st, A, keys, r, rec); break;
+    default: hipLaunchKernelGGL(k_cohen_colmin<16>, grid, dim3(256), 0, st, A, keys, r, rec); break;
     }
+}
+
+// Column records without key minima: first row, last row, length.
+__global__ __launch_bounds__(256) void k_col_records(DevCSC A, float *__restrict__ rec)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.ncols;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a0 = A.colptr[k], a1 = A.colptr[k + 1];
+        const int len = (int)(a1 - a0);
+        *(int4 *)(rec + k * 4) = make_int4(len ? A.rowidx[a0] : 0, len ? A.rowidx[a1 - 1] : 0, len, 0);
+    }
+}
+
+void launch_col_records(const DevCSC &A, float *rec, hipStream_t st)
+{
+    if (A.ncols == 0) return;
+    const int64_t blocks = std::min<int64_t>((A.ncols + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_col_records, dim3((unsigned)blocks), dim3(256), 0, st, A, rec);
 }
 
 
