@@ -120,6 +120,31 @@ def test_prune_parity(mcl, S, R, theta):
     assert st["n_recovered"] == int((info["mode"] == 1).sum())
 
 
+def test_prune_exact_ties(mcl):
+    """Select / recover thresholds that fall on tied values: every tie is kept
+    (columns with <= 64 and > 64 tied candidates, values differing only in the
+    last bit, and a recovery column of equal sub-threshold values)."""
+    x = 0.25
+    xu = float(np.nextafter(x, 1.0))
+    cols = [np.full(50, 0.02),                                    # select, 50 tied
+            np.full(100, 0.01),                                   # select, 100 tied
+            np.concatenate([0.5 + 1e-3 * np.arange(5), np.full(40, 0.003)]),
+            np.array([xu, x] * 10),                               # 10th largest = x + 1 ulp
+            np.full(200, 1e-5)]                                   # recover, 200 tied
+    colptr = np.zeros(len(cols) + 1, np.int64)
+    rows, vals = [], []
+    for j, c in enumerate(cols):
+        colptr[j + 1] = colptr[j] + len(c)
+        rows.append(np.arange(0, 2 * len(c), 2, dtype=np.int32))
+        vals.append(c.astype(np.float64))
+    B = CSC(400, len(cols), colptr, np.concatenate(rows), np.concatenate(vals))
+    O, info = oracle.prune(B, theta=1e-4, select=10, recover=80, pct=0.9)
+    assert list(info["mode"]) == [2, 2, 2, 2, 1]
+    assert list(np.diff(O.colptr)) == [50, 100, 45, 10, 200]
+    G, st = mcl.prune(up(mcl, B), prune_threshold=1e-4, select_num=10, recover_num=80)
+    assert_same_matrix(G.to_host(), O, exact=True)
+
+
 def test_inflate_parity(mcl):
     A = oracle.normalize(planted_graph(5000, 160, s_cap=500, seed=15))
     B, _, _ = oracle.expand(A, A)
@@ -295,6 +320,44 @@ def test_merge_partials_parity(mcl):
     # groups of the binary-merge schedule give the oracle's grouped sums
     g12, _ = mcl.merge_partials([up(mcl, parts[0]), up(mcl, parts[1])])
     assert_same_matrix(g12.to_host(), oracle.merge(parts[:2]), exact=True)
+
+
+def _random_parts(nparts, nrows, ncols, col_len, seed):
+    """nparts matrices with sorted, unique rows per column; column j of every
+    part draws col_len(j) rows from a shared pool, so rows repeat across parts."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for p in range(nparts):
+        colptr = [0]
+        rows, vals = [], []
+        for j in range(ncols):
+            m = min(col_len(j), nrows)
+            r = np.sort(rng.choice(nrows, size=m, replace=False)).astype(np.int32)
+            rows.append(r)
+            vals.append(rng.random(m) + 0.01)
+            colptr.append(colptr[-1] + m)
+        parts.append(CSC(nrows, ncols, np.array(colptr, np.int64), np.concatenate(rows),
+                         np.concatenate(vals)))
+    return parts
+
+
+def test_merge_large_columns_and_empty_columns(mcl):
+    # columns from 1 to 12,000 merged entries (several LDS bins and the HBM
+    # table); column 3 is empty in every part
+    sizes = {0: 3000, 1: 1100, 2: 40, 3: 0, 4: 1025, 5: 2500, 6: 1}
+    parts = _random_parts(4, 6000, 7, lambda j: sizes[j], seed=91)
+    assert max(sum(int(np.diff(p.colptr)[j]) for p in parts) for j in range(7)) > 8192
+    G, _ = mcl.merge_partials([up(mcl, p) for p in parts])
+    assert_same_matrix(G.to_host(), oracle.merge(parts), exact=True)
+
+
+def test_merge_many_parts(mcl):
+    # many parts, and the first 32 of them
+    parts = _random_parts(40, 500, 60, lambda j: 5 + (7 * j) % 40, seed=92)
+    G, _ = mcl.merge_partials([up(mcl, p) for p in parts])
+    assert_same_matrix(G.to_host(), oracle.merge(parts), exact=True)
+    G2, _ = mcl.merge_partials([up(mcl, p) for p in parts[:32]])
+    assert_same_matrix(G2.to_host(), oracle.merge(parts[:32]), exact=True)
 
 
 # ---------------------------------------------------------------- errors
