@@ -362,8 +362,7 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
 {
     (void)policy;  // the multi-pass kernel of the largest columns needs it too
     if (a.A.ncols <= 0 || a.A.nnz > mcl::SLICE_MAX_NNZ) return;  // larger A: shared-table kernels
-    // one entry past the last holds hash 0xFFFFFFFF (no row) and value 0:
-    // masked-off lanes load it
+    // one entry past the last holds row -1 and value 0: masked-off lanes load it
     const int64_t nz = a.A.nnz;
     int32_t *ro = mem.ws<int32_t>(nz + 1);
     double *vo = mem.ws<double>(nz + 1);
@@ -371,10 +370,13 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
     HIPC(hipMemsetAsync(ro + nz, 0xFF, sizeof(int32_t), mem.st));
     HIPC(hipMemsetAsync(vo + nz, 0, sizeof(double), mem.st));
     mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
-    a.shash = ro;
+    // every kernel reads the sliced copy (same columns, rows grouped by hash)
+    a.A.rowidx = ro;
+    a.A.val = vo;
+    a.srow = ro;
     a.sval = vo;
     a.goff = go;
-    a.src_end = (int32_t)nz;
+    a.src_end = (uint32_t)nz;
 }
 
 // Runs the numeric phase for the columns binned in `pl`, then resolves table

@@ -37,15 +37,6 @@ __device__ __forceinline__ T ldg(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
-// Element `i` of a global array addressed with a 32-bit byte offset from a
-// wave-uniform base (the caller guarantees i * sizeof(T) < 2^32).
-template <typename T>
-__device__ __forceinline__ T ldg_u32(const T *base, uint32_t i)
-{
-    return *(const __attribute__((address_space(1))) T *)((const char *)base +
-                                                          (uint64_t)(i * (uint32_t)sizeof(T)));
-}
-
 // Xor-butterfly sum over the 64 lanes.  Lane l and lane l^d always add the
 // same two operands (in swapped order), so every lane ends with the same,
 // schedule-independent value.

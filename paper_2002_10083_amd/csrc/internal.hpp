@@ -43,16 +43,16 @@ struct NumericArgs {
     int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
-    const int32_t *shash;     // sliced copy of A (column ranges of A.colptr): row hashes
+    const int32_t *srow;     // sliced copy of A (column ranges of A.colptr): rows
     const double *sval;       //   and values
-    int32_t src_end;          // sliced copy: index of the entry past the last (hash 0xFFFFFFFF, value 0)
+    uint32_t src_end;         // sliced copy: index of the entry past the last (row -1, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
 };
 
 // ---- spgemm.hip
 constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced source layout
-// the sliced kernels address the sliced copy of A with 32-bit byte offsets
-constexpr int64_t SLICE_MAX_NNZ = (int64_t{1} << 29) - 1;
+// the sliced kernels index the sliced copy of A (and its sentinel) with 32-bit entry indices
+constexpr int64_t SLICE_MAX_NNZ = (int64_t{1} << 32) - 2;
 constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin
@@ -64,7 +64,7 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
                           hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
-// sliced copy of A: row hashes and values, each column ordered by row group, + group boundaries
+// sliced copy of A: rows and values, each column ordered by row group, + group boundaries
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
 // Cohen keys per row are stored with this stride (r rounded up to 4)
 inline int cohen_stride(int r) { return (r + 3) & ~3; }

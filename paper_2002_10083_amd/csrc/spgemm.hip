@@ -1377,9 +1377,10 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 // Rows are dealt to NG = 64 groups by the top six bits of their
 // multiplicative hash.  The sliced copy of a source matrix keeps every column
 // in place but orders its entries by group (in no particular order inside a
-// group), stores each row as its hash (a bijection of 32-bit words, so the
-// tables key on it directly and the bucket bits need no multiply) and
-// records the 65 group boundaries of the column.  A workgroup of NW
+// group) and records the 65 group boundaries of the column.  Every kernel
+// reads the sliced copy: the HBM tables take their bucket from the top bits
+// of the same hash, so consecutive entries also land in one region of an HBM
+// table.  A workgroup of NW
 // waves then gives wave w the groups [w*G, (w+1)*G), G = NG/NW, with a
 // private table of SW slots: the entries of A_*k that wave w needs are one
 // contiguous, exactly known run, waves never share a row, so accumulation
@@ -1390,15 +1391,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 constexpr int NG = SLICE_GROUPS;
 static_assert(NG == WAVE, "one group per lane in the layout pass");
 
-// Row hash: multiplication by an odd constant, inverted by its inverse modulo
-// 2^32.  No row below 2^31 hashes to 0xFFFFFFFF (EMPTY_KEY): that word is the
-// hash of row -ROW_HASH_INV mod 2^32 = 0xF174D0AF.
-constexpr uint32_t ROW_HASH_MUL = 2654435761u;
-constexpr uint32_t ROW_HASH_INV = 0x0E8B2F51u;
-static_assert(ROW_HASH_MUL * ROW_HASH_INV == 1u, "inverse modulo 2^32");
-static_assert(0u - ROW_HASH_INV > 0x7FFFFFFFu, "no row < 2^31 hashes to EMPTY_KEY");
-__device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * ROW_HASH_MUL; }
-__device__ __forceinline__ int32_t row_of_hash(int32_t h) { return (int32_t)((uint32_t)h * ROW_HASH_INV); }
+__device__ __forceinline__ uint32_t row_hash(int32_t r) { return (uint32_t)r * 2654435761u; }
 __device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >> 26); }
 // home bucket inside a sub-table of 2^logNB buckets: the hash bits below the group bits
 __device__ __forceinline__ uint32_t hash_bucket(uint32_t h, int logNB) { return (h << 6) >> (32 - logNB); }
@@ -1429,9 +1422,9 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
     c[lane()] = cur;
     group_sync<WAVE>();
     for (int e = lane(); e < len; e += WAVE) {
-        const uint32_t h = row_hash(A.rowidx[p0 + e]);
-        const int64_t d = p0 + atomicAdd(&c[h >> 26], 1);
-        rowo[d] = (int32_t)h;
+        const int32_t r = A.rowidx[p0 + e];
+        const int64_t d = p0 + atomicAdd(&c[row_group(r)], 1);
+        rowo[d] = r;
         valo[d] = A.val[p0 + e];
     }
 }
@@ -1444,8 +1437,7 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 }
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
-// table of SW slots (cleared here), keyed by row hash.  Returns the number of
-// keys it placed; *wovf is raised when a probe fails; more than capw keys
+// table of SW slots (cleared here).  Returns the number of keys it placed; *wovf is raised when a probe fails; more than capw keys
 // stop the accumulation early (the caller treats both as overflow).
 // col_keys / col_cap: a counter shared by the column's waves and the
 // column's key capacity; a wave stops soon after the column total exceeds it
@@ -1484,22 +1476,24 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             b = a.B.val[bs + t];
         }
     };
-    auto run_of = [&](int k, int &ws, int &len) {
+    auto run_of = [&](int k, uint32_t &ws, int &len) {
         ws = 0;
         len = 0;
         if (k >= 0) {
             const int32_t *go = a.goff + (int64_t)k * (NG + 1);
             const int r0 = go[g0], r1 = go[g1];
-            ws = (int)a.A.colptr[k] + r0;  // the sliced copy has fewer than 2^29 entries
+            ws = (uint32_t)a.A.colptr[k] + (uint32_t)r0;  // the sliced copy has fewer than 2^32 entries
             len = r1 - r0;
         }
     };
-    int kn, wsn, lenn;
+    int kn, lenn;
+    uint32_t wsn;
     double bvn;
     step_of(0, kn, bvn);
     run_of(kn, wsn, lenn);
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
-        const int ws = wsn, len = lenn;
+        const uint32_t ws = wsn;
+        const int len = lenn;
         const double bv = bvn;
         bool next_runs = tb + WAVE < mj;  // the next batch's runs are still to be loaded
         if (next_runs) step_of(tb + WAVE, kn, bvn);
@@ -1522,11 +1516,11 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         };
         // lane l's run as an offset into A: entry f of the packed sequence,
         // f in [pre_l, pre_l + len_l), is A entry f + base_l
-        const int basev = ws - pre;
+        const uint32_t basev = ws - (uint32_t)pre;  // modulo 2^32
         auto issue = [&](Grp &G, int c0) {
             // two sweeps: the lane permutes of all D chunks first (one wait
             // for all of them), then the addresses and the loads
-            int bu[D];
+            uint32_t bu[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
@@ -1539,7 +1533,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 int rank = 0;
                 for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
                 const int u = cnt0 - 1 + rank;
-                bu[i] = shfl_i(basev, u);
+                bu[i] = (uint32_t)shfl_i((int)basev, u);
                 if (MODE != MODE_COUNT) G.bb[i] = shfl_d(bv, u);
                 G.sub[i] = rank;  // position of the lane's step among the chunk's steps
                 G.nsub[i] = k + 1;
@@ -1547,10 +1541,10 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
-                // past the run ends: the sentinel entry (hash 0xFFFFFFFF, value 0)
-                const uint32_t ad = (F + lane() < total) ? (uint32_t)(bu[i] + F + lane()) : (uint32_t)a.src_end;
-                G.rr[i] = ldg_u32(a.shash, ad);
-                if (MODE != MODE_COUNT) G.vv[i] = ldg_u32(a.sval, ad);
+                // past the run ends: the sentinel entry (row -1, value 0)
+                const uint32_t ad = (F + lane() < total) ? bu[i] + (uint32_t)(F + lane()) : a.src_end;
+                G.rr[i] = ldg(a.srow + (uint64_t)ad);
+                if (MODE != MODE_COUNT) G.vv[i] = ldg(a.sval + (uint64_t)ad);
             }
         };
         auto fold = [&](Grp &G) {
@@ -1558,7 +1552,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             keys4 kb[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                hb[i] = hash_bucket((uint32_t)G.rr[i], LOGNBW);
+                hb[i] = sub_bucket(G.rr[i], LOGNBW);
                 kb[i] = load_bucket<true>(wkey, hb[i]);
             }
             const int col_total = __hip_atomic_load((__attribute__((address_space(3))) int *)col_keys,
@@ -1674,12 +1668,6 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
-    // keys back from hashes to rows, in place (slot positions stay those of the hash)
-    for (int s = tid; s < STOT; s += NT) {
-        const int32_t h = sh.key[s];
-        if (h != EMPTY_KEY) sh.key[s] = row_of_hash(h);
-    }
-    __syncthreads();
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
     const int32_t lo = a.lo[j];
@@ -1770,7 +1758,7 @@ __global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
             const uint64_t mk = ballot(k != EMPTY_KEY);
             if (k != EMPTY_KEY) {
                 const int64_t d = base + off + pre + run + popc_below(mk);
-                a.out_row[d] = row_of_hash(k);
+                a.out_row[d] = k;
                 if (MODE != MODE_COUNT) a.out_val[d] = wval[s0 + lane()];
             }
             run += __popcll(mk);
