@@ -95,7 +95,7 @@ def test_symbolic_flops_and_exact_nnz(mcl):
 
 def test_cohen_estimate_matches_oracle(mcl):
     A = oracle.normalize(planted_graph(4000, 150, s_cap=400, seed=13))
-    for r in (3, 5, 10):
+    for r in (2, 3, 5, 10, 12, 16):  # every padded key stride (4, 8, 12, 16)
         ref = oracle.cohen_estimate(A, A, r=r, seed=77, it=3)
         est = mcl.estimate(up(mcl, A), up(mcl, A), estimator=mcl.EST_COHEN, cohen_keys=r, seed=77,
                            iteration=3).cpu().numpy()
