@@ -1378,10 +1378,10 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 // multiplicative hash.  The sliced copy of a source matrix keeps every column
 // in place but orders its entries by group (in no particular order inside a
 // group) and records the 65 group boundaries of the column.  Every kernel
-// reads the sliced copy: the HBM tables take their bucket from the top bits
-// of the same hash, so consecutive entries also land in one region of an HBM
-// table.  A workgroup of NW
-// waves then gives wave w the groups [w*G, (w+1)*G), G = NG/NW, with a
+// of a product reads the sliced copy: the HBM tables take their bucket from
+// the top bits of the same hash, so consecutive entries also probe one region
+// of an HBM table.  A workgroup of NW waves then gives wave w the groups
+// [w*G, (w+1)*G), G = NG/NW, with a
 // private table of SW slots: the entries of A_*k that wave w needs are one
 // contiguous, exactly known run, waves never share a row, so accumulation
 // needs no barrier, and a wave's LDS operations apply in issue order, which
@@ -1437,8 +1437,9 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 }
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
-// table of SW slots (cleared here).  Returns the number of keys it placed; *wovf is raised when a probe fails; more than capw keys
-// stop the accumulation early (the caller treats both as overflow).
+// table of SW slots (cleared here).  Returns the number of keys it placed;
+// *wovf is raised when a probe fails; more than capw keys stop the
+// accumulation early (the caller treats both as overflow).
 // col_keys / col_cap: a counter shared by the column's waves and the
 // column's key capacity; a wave stops soon after the column total exceeds it
 // (the total is read with the next group's bucket reads, so no LDS round
