@@ -378,6 +378,21 @@ __device__ __forceinline__ int wave_reserve(int32_t *counters, int c, bool valid
     return pos;
 }
 
+// Workgroup-aggregated reservation: the waves first combine their counts in
+// LDS (lcnt, lbase: NC ints each), then every class costs one global atomic
+// per workgroup and call.  Called by all threads of the workgroup.
+template <int NC>
+__device__ __forceinline__ int block_reserve(int32_t *counters, int c, bool valid, int32_t *lcnt, int32_t *lbase)
+{
+    if (threadIdx.x < NC) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int wpos = wave_reserve<NC>(lcnt, c, valid);
+    __syncthreads();
+    if (threadIdx.x < NC) lbase[threadIdx.x] = lcnt[threadIdx.x] ? atomicAdd(&counters[threadIdx.x], lcnt[threadIdx.x]) : 0;
+    __syncthreads();
+    return valid ? lbase[c] + wpos : 0;
+}
+
 __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__restrict__ flops,
                                               const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
                                               const float *__restrict__ est, int est_kind,
@@ -387,6 +402,12 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
                                               int32_t *__restrict__ bin_count,
                                               unsigned long long *__restrict__ max_global)
 {
+    // bin counts and the largest HBM-table size are combined per workgroup
+    __shared__ int32_t lcnt[NUM_LDS_BINS + 1];
+    __shared__ unsigned long long lmax;
+    if (threadIdx.x <= NUM_LDS_BINS) lcnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) lmax = 0;
+    __syncthreads();
     for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = j0 + threadIdx.x;
         const bool act = j < ncols && !(col_active && !col_active[j]);
@@ -410,9 +431,12 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
         if (b == NUM_LDS_BINS && try_lds) b = NUM_LDS_BINS - 1;
         bin[j] = b;
         capv[j] = (b < NUM_LDS_BINS) ? bin_cap_c(b) : need;
-        wave_reserve<NUM_LDS_BINS + 1>(bin_count, b, true);
-        if (b == NUM_LDS_BINS) atomicMax(max_global, (unsigned long long)need);
+        wave_reserve<NUM_LDS_BINS + 1>(lcnt, b, true);
+        if (b == NUM_LDS_BINS) atomicMax(&lmax, (unsigned long long)need);
     }
+    __syncthreads();
+    if (threadIdx.x <= NUM_LDS_BINS && lcnt[threadIdx.x]) atomicAdd(&bin_count[threadIdx.x], lcnt[threadIdx.x]);
+    if (threadIdx.x == 0 && lmax) atomicMax(max_global, lmax);
 }
 
 void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const int32_t *hi,
@@ -421,7 +445,7 @@ void launch_plan(int64_t ncols, const int64_t *flops, const int32_t *lo, const i
                  int64_t *max_global, hipStream_t st)
 {
     if (ncols == 0) return;
-    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 1024);
     hipLaunchKernelGGL(k_plan, dim3(grid), dim3(256), 0, st, ncols, flops, lo, hi, est, est_kind,
                        est_scale, nrows, col_active, bin, capv, bin_count,
                        (unsigned long long *)max_global);
@@ -434,20 +458,25 @@ __global__ __launch_bounds__(256) void k_phase_plan(int64_t n, const int32_t *__
                                                     int32_t *__restrict__ ph_bin, int64_t *__restrict__ ph_base,
                                                     int32_t *__restrict__ counts)
 {
+    __shared__ int32_t lcnt[NUM_LDS_BINS + 1];
+    if (threadIdx.x <= NUM_LDS_BINS) lcnt[threadIdx.x] = 0;
+    __syncthreads();
     for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < n; j0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = j0 + threadIdx.x;
         const int b = (j >= c0 && j < c1) ? bin[j] : -1;
         if (j < n) ph_bin[j] = b;
         if (b >= 0) ph_base[j] = base[j] - base[c0];
-        wave_reserve<NUM_LDS_BINS + 1>(counts, b, b >= 0);
+        wave_reserve<NUM_LDS_BINS + 1>(lcnt, b, b >= 0);
     }
+    __syncthreads();
+    if (threadIdx.x <= NUM_LDS_BINS && lcnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
 }
 
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st)
 {
     if (n <= 0) return;
-    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_phase_plan, dim3(grid), dim3(256), 0, st, n, bin, base, c0, c1, ph_bin, ph_base,
                        counts);
 }
@@ -655,10 +684,11 @@ __global__ __launch_bounds__(256) void k_scatter_bins(int64_t ncols, const int32
                                                       BinOffsets bin_off, int32_t *__restrict__ cursor,
                                                       int32_t *__restrict__ lists)
 {
+    __shared__ int32_t lcnt[NUM_LDS_BINS + 1], lbase[NUM_LDS_BINS + 1];
     for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = j0 + threadIdx.x;
         const int b = (j < ncols) ? bin[j] : -1;
-        const int pos = wave_reserve<NUM_LDS_BINS + 1>(cursor, b, b >= 0);
+        const int pos = block_reserve<NUM_LDS_BINS + 1>(cursor, b, b >= 0, lcnt, lbase);
         if (b >= 0) lists[bin_off.off[b] + pos] = (int32_t)j;
     }
 }
@@ -667,7 +697,7 @@ void launch_scatter_bins(int64_t ncols, const int32_t *bin, const BinOffsets &bi
                          int32_t *lists, hipStream_t st)
 {
     if (ncols == 0) return;
-    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
+    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 1024);
     hipLaunchKernelGGL(k_scatter_bins, dim3(grid), dim3(256), 0, st, ncols, bin, bin_off, cursor,
                        lists);
 }
