@@ -62,11 +62,24 @@ def bin_bytes(st, b):
             + BYTES_PER_OUT * st["bin_out"][b] + BYTES_PER_COL * st["bin_cols"][b])
 
 
-def cpu_baseline(W, target_s=12.0, seed=7):
-    """The CPU oracle (expand + prune + inflate) on a random sample of columns."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, target_s=12.0, seed=7, single_s=6.0):
+    """The CPU oracle (expand + prune + inflate) on a random sample of columns
+    of the same column-stochastic A the GPU iterated (downloaded from the
+    device), on all threads and on one thread.  Returns the baseline record
+    and the sample (columns, unpruned product, prune info, result) for the
+    parity check of the GPU output."""
     import numpy as np
     import oracle
-    A = oracle.normalize(W)
     rng = np.random.default_rng(seed)
     n = A.ncols
 
@@ -75,18 +88,84 @@ def cpu_baseline(W, target_s=12.0, seed=7):
         Bs = A.restrict_columns(cols)
         t = time.perf_counter()
         C, flops, nnz = oracle.expand(A, Bs)
-        P, _ = oracle.prune(C)
-        oracle.inflate(P, 2.0)
-        return time.perf_counter() - t, int(flops.sum()), int(nnz.sum()), len(cols)
+        P, info = oracle.prune(C)
+        I = oracle.inflate(P, 2.0)
+        return time.perf_counter() - t, int(flops.sum()), int(nnz.sum()), cols, C, info, I
 
-    dt, fl, nz, k = run(0.002)
+    threads = oracle.num_threads()
+    dt, fl, nz, cols, _, _, _ = run(0.002)
     frac = min(1.0, 0.002 * target_s / max(dt, 1e-3))
-    dt, fl, nz, k = run(frac)
-    return {"value": round(fl / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d of %d columns (uniform, seed %d): expand+prune+inflate, %.1f s, "
-                      "%.3g multiply-adds, %.3g product nnz/s"
-                      % (k, n, seed, dt, fl, nz / dt)}
+    dt, fl, nz, cols, C, info, I = run(frac)
+    rec = {"value": round(fl / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "%d of %d columns (uniform, seed %d) of the GPU's normalised input: "
+                     "expand+prune+inflate, %.1f s on %d threads, %.3g multiply-adds, %.3g product nnz/s"
+                     % (len(cols), n, seed, dt, threads, fl, nz / dt)}
+    # single thread, on a smaller sample of the same kind
+    oracle.set_num_threads(1)
+    try:
+        dt1, fl1, _, cols1, _, _, _ = run(min(1.0, frac * single_s / max(dt * threads, 1e-3)))
+    finally:
+        oracle.set_num_threads(threads)
+    rec["single_thread"] = {"value": round(fl1 / dt1 / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
+                            "sample": "%d columns, %.1f s" % (len(cols1), dt1)}
+    return rec, (cols, C, info, I)
+
+
+def gpu_parity(G, sample, theta=1e-4, pct=0.9, rtol=1e-12):
+    """Compares the GPU's fused iteration on the sampled columns with the
+    oracle's expand + prune + inflate of the same columns: row patterns must
+    be identical and values within rtol, except where a column's kept set
+    differs only by entries within 1e-12 (relative) of its threshold, or its
+    recovery test is within 1e-12 of equality (near-ties, accepted either
+    way)."""
+    import numpy as np
+    import torch
+    cols, C, info, I = sample
+    ct = torch.from_numpy(cols.astype(np.int64)).to(G.colptr.device)
+    s = G.colptr[ct]
+    cnt = G.colptr[ct + 1] - s
+    total = int(cnt.sum())
+    start = torch.cumsum(cnt, 0) - cnt
+    idx = torch.repeat_interleave(s - start, cnt) + torch.arange(total, device=s.device)
+    grow = G.rowidx[idx].cpu().numpy()
+    gval = G.val[idx].cpu().numpy()
+    gcnt = cnt.cpu().numpy()
+    gcp = np.zeros(len(cols) + 1, np.int64)
+    gcp[1:] = np.cumsum(gcnt)
+    ocnt = np.diff(I.colptr)
+    same_len = gcnt == ocnt
+    # columns of equal length: compare rows in bulk
+    col_of = np.repeat(np.arange(len(cols)), ocnt)
+    eq_len_entry = same_len[col_of]
+    gpos = (gcp[:-1] - I.colptr[:-1])[col_of] + np.arange(I.nnz)
+    row_ok = np.ones(I.nnz, bool)
+    row_ok[eq_len_entry] = grow[gpos[eq_len_entry]] == I.rowidx[eq_len_entry]
+    bad_col = ~same_len
+    np.logical_or.at(bad_col, col_of, ~row_ok)
+    good_entry = ~bad_col[col_of]
+    rel = np.abs(gval[gpos[good_entry]] - I.val[good_entry]) / I.val[good_entry]
+    max_rel = float(rel.max(initial=0.0))
+    bad_val = int((rel > rtol).sum())
+    near = unexplained = 0
+    for q in np.nonzero(bad_col)[0]:
+        mB, mP, t = info["mass"][q], info["mass_above"][q], info["threshold"][q]
+        gq = grow[gcp[q]:gcp[q + 1]]
+        gr = set(gq.tolist())
+        orr = set(I.rowidx[I.colptr[q]:I.colptr[q + 1]].tolist())
+        # a near-tie changes the kept set; rows out of order or repeated never pass
+        ok = gr != orr and bool(np.all(np.diff(gq) > 0))
+        if ok and not abs(mP - pct * mB) <= 1e-12 * mB:
+            r0, v0 = C.column(q)
+            vals = dict(zip(r0.tolist(), v0.tolist()))
+            ok = all(r in vals and (abs(vals[r] - t) <= 1e-12 * t or abs(vals[r] - theta) <= 1e-12 * theta)
+                     for r in gr ^ orr)
+        near += ok
+        unexplained += not ok
+    return {"columns": int(len(cols)), "entries": int(I.nnz), "mismatches": unexplained + bad_val,
+            "near_tie_columns": near, "max_rel_diff": max_rel, "rtol": rtol,
+            "rule": "row patterns identical, values within rtol; kept sets may differ only by "
+                    "entries within 1e-12 of the column threshold (near-ties)"}
 
 
 def _line(metric, value, unit, ms, higher, workload, extra, steps=1, warmup=0, dtype="f64"):
@@ -98,7 +177,7 @@ def _line(metric, value, unit, ms, higher, workload, extra, steps=1, warmup=0, d
 
 
 def bench_merge(args):
-    """Section 5 / Alg. 2: the inner dimension of A*A (1M-vertex planted graph)
+    """Section 4 / Alg. 2: the inner dimension of A*A (1M-vertex planted graph)
     cut into 8 SUMMA stages; partial products merged by the binary schedule
     vs all at once."""
     import torch
@@ -169,7 +248,7 @@ def bench_batched(args, sample=300, seed=5):
         blk = mcl.DeviceCSC.from_host(drivers.component_block(An, c0, c1))
         torch.cuda.synchronize()
         t = time.perf_counter()
-        Bf, it = drivers.component_mcl(blk, params)
+        Bf, it, _ = drivers.component_mcl(blk, params)
         torch.cuda.synchronize()
         t_loop += time.perf_counter() - t
         same &= bool(it == iters[c]) and drivers.same_block(Af, c0, c1, Bf)
@@ -302,10 +381,11 @@ def main():
     torch.cuda.synchronize()
     sts = []
     t = time.perf_counter()
+    G = None
     for i in range(args.steps):
+        del G
         G, change, st = mcl.iterate(A, params)
         sts.append(st)
-        del G
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     ms_step = dt / args.steps * 1e3
@@ -358,10 +438,14 @@ def main():
     log("bins ms:", [round(x, 2) for x in mean_ms])
     if not args.no_cpu_baseline:
         t1 = time.time()
-        out["cpu_baseline"] = cpu_baseline(W)
+        out["cpu_baseline"], sample = cpu_baseline(A.to_host())
         log("cpu baseline took %.1f s" % (time.time() - t1))
+        t1 = time.time()
+        out["parity"] = gpu_parity(G, sample)
+        log("parity check took %.1f s: %s" % (time.time() - t1, out["parity"]))
     else:
         out["cpu_baseline"] = None
+        out["parity"] = None
     print(json.dumps(out), flush=True)
 
 

@@ -6,8 +6,8 @@
  * recovery per column), inflation (Hadamard power, then column
  * re-normalisation), and the change between successive iterates.  Also the
  * merge of the partial products one process forms across its Sparse SUMMA
- * stages (Section 2 "Overview of Sparse SUMMA", Section 5 and Alg. 2), the
- * probabilistic output-size estimator (Section 6) and a learned replacement
+ * stages (Section 2 "Overview of Sparse SUMMA", Section 4 and Alg. 2), the
+ * probabilistic output-size estimator (Section 5) and a learned replacement
  * for it.
  *
  * Conventions shared by every entry point
@@ -58,7 +58,7 @@ extern "C" {
 
 /* Output-size estimator used to size the per-column hash tables. */
 #define MCL_EST_BOUND 0   /* exact-safe bound min(flops_j, row span_j) */
-#define MCL_EST_COHEN 1   /* Cohen's exponential-key estimate (Section 6) */
+#define MCL_EST_COHEN 1   /* Cohen's exponential-key estimate (Section 5) */
 #define MCL_EST_MLP 2     /* learned estimate (mcl_mlp_forward) */
 
 typedef struct {
@@ -151,10 +151,18 @@ int mcl_prune(const mcl_csc *B, mcl_csc *C, const mcl_params *params,
  * If colsum_err_max is not NULL it receives max_j |sum_i a_ij - 1| (host). */
 int mcl_inflate(mcl_csc *C, double r, void *stream, double *colsum_err_max);
 
-/* One fused MCL iteration: A_next = inflate(prune(A*A)).  Bit-identical to
- * mcl_inflate(mcl_prune(mcl_expand(A, A))).  max_change receives (host)
+/* One fused MCL iteration -- the body of the loop of Alg. 1 (Section 2
+ * "Overview of the MCL algorithm"): expansion, prune, inflation and the
+ * change that the loop condition tests.  A_next = inflate(prune(A*A)),
+ * bit-identical to mcl_inflate(mcl_prune(mcl_expand(A, A))).  A must be
+ * square.  A_next's arrays come from `alloc` (the caller owns them).
+ * max_change receives (host)
  * max_{i,j} |a_next_ij - a_ij| over the union of both patterns -- one value,
- * or one per component when comp_ptr is given.
+ * or one per component when comp_ptr is given.  Errors: MCL_EINVAL for a
+ * non-square A, bad parameters or (with validate) a malformed A; MCL_ENOMEM
+ * when the allocator fails; MCL_EHIP for a runtime error.  A column whose
+ * estimated table overflows is recomputed (one bin larger, then sized by an
+ * exact symbolic count), so the result never depends on the estimate.
  * Batched form: comp_ptr (device int64[ncomp+1]) splits the vertices into
  * ncomp contiguous ranges whose blocks are closed under A (block-diagonal A);
  * `active` (device uint8[ncomp]) selects the components to iterate: columns
@@ -164,20 +172,37 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
                 const uint8_t *active, const mcl_params *params, const mcl_allocator *alloc,
                 void *stream, mcl_stats *stats, double *max_change);
 
-/* Sparse SUMMA merge (Section 2 "Overview of Sparse SUMMA", Section 5):
+/* Clusters of Alg. 1 (its last step; Section 2 "Overview of the MCL
+ * algorithm"): the connected components of the pattern of a square A,
+ * treated as undirected (vertices i and j are joined when a_ij or a_ji is
+ * stored; weak connectivity of the directed pattern).  labels (device
+ * int32[ncols], caller-owned) receives for every vertex the smallest vertex
+ * id of its component, so labels are unique for a given pattern whatever the
+ * schedule.  ncomp (host, nullable) receives the number of components.
+ * Values of A are not read.  Errors: MCL_EINVAL for a non-square A or NULL
+ * labels with ncols > 0; MCL_ENOMEM / MCL_EHIP as elsewhere. */
+int mcl_components(const mcl_csc *A, int32_t *labels, int64_t *ncomp, const mcl_allocator *alloc,
+                   void *stream);
+
+/* Sparse SUMMA merge (Section 2 "Overview of Sparse SUMMA", Section 4):
  * C = sum of nparts same-shape matrices (`parts` is a HOST array of
  * descriptors whose arrays are device pointers).  Equal rows are summed in
  * array order: (((p0 + p1) + p2) + ...). */
 int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C,
                        const mcl_allocator *alloc, void *stream, mcl_stats *stats);
 
-/* Symbolic pass: flops_j (device int64[ncols of B]) and, when nnz_per_col is
- * not NULL, the exact nnz of every product column (insert-only hash count). */
+/* Symbolic pass of C = A*B: flops_j = sum_{k in B_*j} nnz(A_*k) (Section 2
+ * "Notations"; device int64[ncols of B]) and, when nnz_per_col is not NULL,
+ * the exact nnz of every product column -- the exact symbolic SpGEMM that
+ * Section 5 replaces by an estimate (insert-only hash count; device
+ * int64[ncols of B]).  Both outputs are caller-owned device arrays; values of
+ * A and B are not read.  Errors: MCL_EINVAL for mismatched shapes or NULL
+ * flops_per_col, MCL_ENOMEM / MCL_EHIP as elsewhere. */
 int mcl_symbolic(const mcl_csc *A, const mcl_csc *B, int64_t *flops_per_col,
                  int64_t *nnz_per_col, const mcl_allocator *alloc, void *stream);
 
 /* Per-column output-size estimate (device float[B.ncols]) with the estimator
- * chosen in params (Cohen: Section 6; MLP: learned; BOUND: the exact-safe
+ * chosen in params (Cohen: Section 5; MLP: learned; BOUND: the exact-safe
  * bound).  Also fills the 12 MLP input features per column when `features`
  * (device float[B.ncols * 12]) is not NULL. */
 int mcl_estimate(const mcl_csc *A, const mcl_csc *B, const mcl_params *params, float *est,

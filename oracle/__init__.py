@@ -12,8 +12,8 @@ driven from here through ctypes.  Paper passages followed (arXiv 2002.10083):
   (threshold + top-k per column), inflation (Hadamard power), loop while the
   iterate changes, return the connected components.
 * Section 2 "Notations" -- flops(AB) and the compression factor.
-* Section 5 (binary merge, Alg. 2) -- merge schedule of Sparse SUMMA partials.
-* Section 6 -- Cohen's probabilistic output-nnz estimator.
+* Section 4 (binary merge, Alg. 2) -- merge schedule of Sparse SUMMA partials.
+* Section 5 -- Cohen's probabilistic output-nnz estimator.
 
 Readings of points the paper leaves open (recovery rule, tie handling,
 re-normalisation after inflation, convergence measure) are documented with
@@ -77,6 +77,7 @@ def _declare(lib):
     lib.orc_cohen_estimate.argtypes = [I64, I64, I64, P, P, P, P, I64, ctypes.c_uint64, I64, P]
     lib.orc_merge.argtypes = [I64, ctypes.c_int32, P, P, P, ctypes.c_int, P, P, P, P]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
 
 
 def _p(a: np.ndarray):
@@ -93,6 +94,11 @@ def _prep(M: CSC):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 # ----------------------------------------------------------------------
@@ -229,7 +235,7 @@ def mcl(W: CSC, theta=1e-4, select=1100, recover=1400, pct=0.9, r=2.0, tol=1e-9,
 
 
 # ----------------------------------------------------------------------
-# Section 6: Cohen estimator
+# Section 5: Cohen estimator
 # ----------------------------------------------------------------------
 
 def cohen_key(seed, it, i, l, r) -> float:
@@ -237,7 +243,7 @@ def cohen_key(seed, it, i, l, r) -> float:
 
 
 def cohen_estimate(A: CSC, B: CSC, r=5, seed=0, it=0) -> np.ndarray:
-    """Cohen's estimate of nnz((A B)_*j) for every column j (Section 6)."""
+    """Cohen's estimate of nnz((A B)_*j) for every column j (Section 5)."""
     lib = _load()
     acp, ari, _ = _prep(A)
     bcp, bri, _ = _prep(B)
@@ -248,7 +254,7 @@ def cohen_estimate(A: CSC, B: CSC, r=5, seed=0, it=0) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------
-# Section 5: merging Sparse SUMMA partial products
+# Section 4: merging Sparse SUMMA partial products
 # ----------------------------------------------------------------------
 
 def merge(parts):

@@ -17,7 +17,7 @@
  *     pruning with a threshold and top-k per column, inflation as a Hadamard
  *     power, loop while the matrix changes.
  *   - Section 2, "Notations": flops(AB) = sum_j sum_{i in inds(B_*j)} nnz(A_*i).
- *   - Section 6 (probabilistic memory requirement estimation): Cohen's
+ *   - Section 5 (probabilistic memory requirement estimation): Cohen's
  *     exponential-key estimator with r keys, estimate (r-1)/sum of keys.
  */
 #include <math.h>
@@ -238,7 +238,7 @@ void orc_delta(int64_t ncols,
 }
 
 /* ------------------------------------------------------------------ */
-/* Cohen's probabilistic nnz estimator (Section 6)                      */
+/* Cohen's probabilistic nnz estimator (Section 5)                      */
 /* ------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the t-th output of the
  * generator seeded with s is mix(s + (t + 1) * gamma). */
@@ -304,7 +304,7 @@ void orc_cohen_estimate(int64_t a_nrows, int64_t a_ncols, int64_t b_ncols,
 }
 
 /* ------------------------------------------------------------------ */
-/* multiway merge of partial products (Section 5): per column a k-way   */
+/* multiway merge of partial products (Section 4): per column a k-way   */
 /* heap merge of the sorted lists; equal rows are summed in list order. */
 /* ------------------------------------------------------------------ */
 typedef struct { int32_t row; int32_t list; int64_t pos; } heap_item;
@@ -389,5 +389,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Thread count of later parallel loops (results do not depend on it). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

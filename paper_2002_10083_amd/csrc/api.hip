@@ -380,10 +380,12 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
 }
 
 // Runs the numeric phase for the columns binned in `pl`, then resolves table
-// overflow: overflowed columns move one LDS bin up and are recomputed into a
-// new temp region; columns that overflow the largest LDS bin get an exact
-// count and the HBM table.  `a` carries A/B (or parts), the prune args and
-// the per-column outputs.
+// overflow: overflowed columns move one LDS bin up (the largest LDS bin to
+// the multi-pass kernel) and are recomputed into a new temp region; columns
+// that overflow again, or that overflowed the largest table, get an exact
+// count and an HBM table of exactly that size, which cannot overflow.  So
+// every column is launched at most three times whatever its estimate.  `a`
+// carries A/B (or parts), the prune args and the per-column outputs.
 void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::NumericArgs a,
             ProductPlan &pl, EngineOut &eo, Timer &tm, const int64_t *bcolptr = nullptr,
             uint32_t policy = 0)
@@ -443,13 +445,16 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         if (round == 1) eo.t_numeric = tm.ms(t0, t1);
         if (novf == 0) break;
         if (round == 1) eo.n_overflow = novf;
+        // at most three rounds reach this point (see above); the region table
+        // holds MAX_REGIONS temp regions
         if (round >= mcl::MAX_REGIONS) fail(MCL_EHIP, "table overflow did not resolve");
-        // bump one bin up; the largest LDS bin goes to the exact path
+        // first round: one bin up (the largest LDS bin to the multi-pass
+        // kernel, or the exact path); later rounds: the exact path
         int32_t *counts_d = dev_i + 1;       // 8 counters
         int32_t *nexact_d = dev_i + 9;
         int32_t *exact = mem.ws<int32_t>(novf);
         mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d,
-                         mode != mcl::MODE_COUNT && a.goff && !a.parts, mem.st);
+                         mode != mcl::MODE_COUNT && a.goff && !a.parts, round >= 2, mem.st);
         int32_t hc[9];
         HIPC(hipMemcpyAsync(hc, counts_d, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
         HIPC(hipStreamSynchronize(mem.st));
@@ -556,6 +561,8 @@ void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mc
     } else {
         mcl::launch_col_records(A, rec, mem.st);
     }
+    tm.mark();
+    const size_t ea = tm.ev.size() - 1;
     float *feat = feat_out;
     if (p.estimator == MCL_EST_MLP && !feat) feat = mem.ws<float>(n * 12);
     mcl::launch_symbolic(A, B, pl.flops, pl.lo, pl.hi, rec, r, cohen ? pl.est : nullptr, feat, nullptr,
@@ -582,8 +589,11 @@ void plan_product(Mem &mem, const mcl::DevCSC &A, const mcl::DevCSC &B, const mc
     HIPC(hipMemcpyAsync(&pl.max_global, mg, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
     HIPC(hipMemcpyAsync(&pl.temp_total, pl.base + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
     HIPC(hipStreamSynchronize(mem.st));
-    if (t_sym) *t_sym = tm.ms(e0, e1);
-    if (t_est) *t_est = tm.ms(e1, e2);
+    // estimate time: Cohen's keys and key minima (their finish is fused into
+    // the symbolic pass) or the MLP forward; symbolic time: the pass itself
+    // and, without Cohen keys, the column records it reads
+    if (t_sym) *t_sym = tm.ms(ea, e1) + (cohen ? 0.0 : tm.ms(e0, ea));
+    if (t_est) *t_est = (cohen ? tm.ms(e0, ea) : 0.0) + tm.ms(e1, e2);
 }
 
 // colptr = exclusive scan of cnt; returns nnz (host).
@@ -1086,6 +1096,28 @@ int mcl_estimate(const mcl_csc *A, const mcl_csc *B, const mcl_params *params, f
         plan_product(mem, dA, dB, p, nullptr, pl, tm, nullptr, nullptr, features);
         if (p.estimator == MCL_EST_BOUND) mcl::launch_bound_estimate(n, pl.flops, pl.lo, pl.hi, A->nrows, est, mem.st);
         HIPC(hipStreamSynchronize(mem.st));
+    });
+}
+
+int mcl_components(const mcl_csc *A, int32_t *labels, int64_t *ncomp, const mcl_allocator *alloc,
+                   void *stream)
+{
+    return with_mem(alloc, stream, nullptr, [&](Mem &mem) {
+        check_csc(A, "A");
+        if (A->nrows != A->ncols) fail(MCL_EINVAL, "mcl_components needs a square matrix");
+        const int64_t n = A->ncols;
+        if (n > 0 && !labels) fail(MCL_EINVAL, "labels is NULL");
+        int64_t roots = 0;
+        if (n > 0) {
+            int32_t *parent = mem.ws<int32_t>(n);
+            int64_t *cnt = mem.ws<int64_t>(1);
+            HIPC(hipMemsetAsync(cnt, 0, sizeof(int64_t), mem.st));
+            mcl::launch_components(dev(*A), parent, labels, cnt, mem.st);
+            HIPC(hipGetLastError());
+            HIPC(hipMemcpyAsync(&roots, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+        }
+        HIPC(hipStreamSynchronize(mem.st));
+        if (ncomp) *ncomp = roots;
     });
 }
 

@@ -99,7 +99,8 @@ void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, con
 void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,
                       int region, hipStream_t st);
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, hipStream_t st);
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, bool force_exact,
+                 hipStream_t st);
 void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
                      const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
                      hipStream_t st);
@@ -144,6 +145,10 @@ void launch_normalize(int64_t ncols, const int64_t *colptr, double *val, hipStre
 
 void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
                        int32_t *hi, hipStream_t st);
+
+// ---- components.hip
+// weakly connected components of the pattern of a square A; label = smallest vertex id
+void launch_components(const DevCSC &A, int32_t *parent, int32_t *label, int64_t *nroots, hipStream_t st);
 
 // ---- mlp.hip
 constexpr int MLP_IN = 12, MLP_H = 64;

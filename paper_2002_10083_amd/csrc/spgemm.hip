@@ -237,7 +237,7 @@ void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *
 }
 
 // ---------------------------------------------------------------------------
-// Cohen's estimator (Section 6): exponential keys on the first layer (rows of
+// Cohen's estimator (Section 5): exponential keys on the first layer (rows of
 // A), minimum over each column of A, then over each column of B.
 // ---------------------------------------------------------------------------
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output t of the generator
@@ -613,11 +613,15 @@ void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64
 
 // Overflowed columns move one LDS bin up (twice the table); columns that
 // overflowed the largest LDS bin are flagged for an exact count (bin 7).
+// With force_exact every listed column is flagged for the exact count: a
+// column that overflowed twice is sized from its exact product size, so the
+// overflow rounds end after at most three launches of any column.
 __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, int32_t n,
                                               int32_t *__restrict__ bin, int64_t *__restrict__ capv,
                                               int32_t *__restrict__ bin_count,
                                               int32_t *__restrict__ exact_list,
-                                              int32_t *__restrict__ n_exact, int to_multipass)
+                                              int32_t *__restrict__ n_exact, int to_multipass,
+                                              int force_exact)
 {
     for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
         const int i = i0 + threadIdx.x;
@@ -627,7 +631,8 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
         // LDS bins move one up; the largest LDS bin moves to the multi-pass
         // kernel at its full capacity (when available); the rest go to the
         // exact count
-        const bool up = valid && (b + 1 < NUM_LDS_BINS || (to_multipass && b + 1 == NUM_LDS_BINS));
+        const bool up = valid && !force_exact &&
+                        (b + 1 < NUM_LDS_BINS || (to_multipass && b + 1 == NUM_LDS_BINS));
         if (up) {
             bin[j] = b + 1;
             capv[j] = (b + 1 < NUM_LDS_BINS) ? (int64_t)bin_cap_c(b + 1) : MP_MAX;
@@ -639,12 +644,12 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
 }
 
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, hipStream_t st)
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, bool force_exact, hipStream_t st)
 {
     if (n <= 0) return;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_bump, dim3(grid), dim3(256), 0, st, list, n, bin, capv, bin_count, exact_list,
-                       n_exact, (int)to_multipass);
+                       n_exact, (int)to_multipass, (int)force_exact);
 }
 
 // Per-bin totals of the launched columns: flops, nnz(B_*j), output count.

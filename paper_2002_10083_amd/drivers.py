@@ -3,7 +3,7 @@ only; every arithmetic step runs in the library's kernels).
 
 * ``summa_merge``: the inner dimension of C = A*A is cut into ``nstages``
   contiguous ranges K_1..K_s, stage i contributes the partial product
-  A[:, K_i] * A[K_i, :] (one SUMMA stage of one process, Section 5), and the
+  A[:, K_i] * A[K_i, :] (one SUMMA stage of one process, Section 4), and the
   partials are merged either with the binary schedule of Alg. 2 (after stage
   i, the top 1 + v2(i) lists of the stack are merged, v2 = number of factors
   of two) or all at once after the last stage.  Equal rows are summed in
@@ -114,13 +114,16 @@ def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", 
 
 
 def batched_mcl(A: "mcl.DeviceCSC", comp_ptr: torch.Tensor, params=None, tol: float = 1e-9,
-                max_iter: int = 200):
-    """Iterate every component until its change drops below `tol`; converged
-    components are frozen (copied) by the library.  Returns (A_final,
-    iterations per component, info)."""
+                max_iter: int = 100):
+    """Iterate every component until its change drops below `tol` (Alg. 1's
+    loop, per component); converged components are frozen (copied) by the
+    library.  Returns (A_final, iterations per component, info); info
+    ["converged"] flags the components whose change fell below `tol` within
+    `max_iter` iterations and info["not_converged"] counts the others."""
     ncomp = comp_ptr.numel() - 1
     active = torch.ones(ncomp, dtype=torch.uint8, device=comp_ptr.device)
     iters = np.zeros(ncomp, np.int64)
+    converged = np.zeros(ncomp, bool)
     steps = []
     it = 0
     while it < max_iter:
@@ -129,12 +132,14 @@ def batched_mcl(A: "mcl.DeviceCSC", comp_ptr: torch.Tensor, params=None, tol: fl
         steps.append(dict(ms=(time.perf_counter() - t) * 1e3, active=int(active.sum()), flops=st["flops"]))
         act = active.cpu().numpy().astype(bool)
         iters[act] += 1
+        converged |= act & (change < tol)
         still = act & (change >= tol)
         it += 1
         if not still.any():
             break
         active = torch.from_numpy(still.astype(np.uint8)).to(comp_ptr.device)
-    return A, iters, dict(calls=it, steps=steps)
+    return A, iters, dict(calls=it, steps=steps, converged=converged,
+                          not_converged=int((~converged).sum()))
 
 
 def component_block(W, c0: int, c1: int):
@@ -145,15 +150,19 @@ def component_block(W, c0: int, c1: int):
                (W.rowidx[p0:p1] - c0).astype(np.int32), W.val[p0:p1].copy())
 
 
-def component_mcl(Ablk: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 200):
-    """Plain loop on one component: iterate until the change drops below `tol`."""
+def component_mcl(Ablk: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 100):
+    """Plain loop on one component: iterate until the change drops below
+    `tol`.  Returns (A_final, iterations, converged) -- converged is False
+    when `max_iter` iterations ended with the change still >= `tol`."""
     it = 0
+    converged = False
     while it < max_iter:
         Ablk, change, _ = mcl.iterate(Ablk, params)
         it += 1
         if change < tol:
+            converged = True
             break
-    return Ablk, it
+    return Ablk, it, converged
 
 
 def same_block(Abig: "mcl.DeviceCSC", c0: int, c1: int, Ablk: "mcl.DeviceCSC") -> bool:
@@ -163,3 +172,21 @@ def same_block(Abig: "mcl.DeviceCSC", c0: int, c1: int, Ablk: "mcl.DeviceCSC") -
     cp = Abig.colptr[c0:c1 + 1] - p0
     return (torch.equal(cp, Ablk.colptr) and torch.equal(Abig.rowidx[p0:p1] - c0, Ablk.rowidx)
             and torch.equal(Abig.val[p0:p1], Ablk.val))
+
+
+def run_mcl(A: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 100):
+    """Alg. 1 on the GPU from a column-stochastic A: iterate until the change
+    drops below `tol` (or `max_iter` iterations), then label the connected
+    components of the final pattern.  Returns (A_final, iterations, labels,
+    ncomp, converged); labels is a device int32 tensor (smallest vertex id of
+    each vertex's cluster)."""
+    it = 0
+    converged = False
+    while it < max_iter:
+        A, change, _ = mcl.iterate(A, params, iteration=it)
+        it += 1
+        if change < tol:
+            converged = True
+            break
+    labels, ncomp = mcl.components(A)
+    return A, it, labels, ncomp, converged

@@ -106,6 +106,8 @@ _lib.mcl_symbolic.argtypes = [ctypes.POINTER(_CSC), ctypes.POINTER(_CSC), _P, _P
                               ctypes.POINTER(_Allocator), _P]
 _lib.mcl_estimate.argtypes = [ctypes.POINTER(_CSC), ctypes.POINTER(_CSC), ctypes.POINTER(Params),
                               _P, _P, ctypes.POINTER(_Allocator), _P]
+_lib.mcl_components.argtypes = [ctypes.POINTER(_CSC), _P, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(_Allocator), _P]
 _lib.mcl_mlp_packed_bytes.restype = ctypes.c_size_t
 _lib.mcl_mlp_state_floats.restype = ctypes.c_size_t
 _lib.mcl_mlp_forward.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
@@ -115,7 +117,7 @@ _lib.mcl_mlp_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_flo
 
 #: every symbol include/mcl.h declares
 EXPORTS = ("mcl_default_params", "mcl_normalize", "mcl_expand", "mcl_prune", "mcl_inflate",
-           "mcl_iterate", "mcl_merge_partials", "mcl_symbolic", "mcl_estimate",
+           "mcl_iterate", "mcl_merge_partials", "mcl_components", "mcl_symbolic", "mcl_estimate",
            "mcl_mlp_packed_bytes", "mcl_mlp_forward", "mcl_mlp_state_floats", "mcl_mlp_init",
            "mcl_mlp_train_step", "mcl_last_error")
 
@@ -330,6 +332,19 @@ def merge_partials(parts: Sequence[DeviceCSC]):
     _check(_lib.mcl_merge_partials(arr, len(parts), ctypes.byref(out), ctypes.byref(al.struct),
                                    _stream(), ctypes.byref(st)))
     return _wrap_out(out, al), st.as_dict()
+
+
+def components(A: DeviceCSC):
+    """Connected components of the pattern of a square A (undirected): returns
+    (labels, ncomp) with labels a device int32 tensor holding, per vertex, the
+    smallest vertex id of its component."""
+    al = _allocator()
+    labels = torch.empty(A.ncols, dtype=torch.int32, device="cuda")
+    nc = ctypes.c_int64(0)
+    a = A._c()
+    _check(_lib.mcl_components(ctypes.byref(a), labels.data_ptr() if A.ncols else None,
+                               ctypes.byref(nc), ctypes.byref(al.struct), _stream()))
+    return labels, int(nc.value)
 
 
 def symbolic(A: DeviceCSC, B: DeviceCSC, exact: bool = False):

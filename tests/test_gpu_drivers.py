@@ -70,15 +70,24 @@ def test_batched_mcl_equals_component_loop(drv):
     comp = torch.from_numpy(U.comp_ptr).cuda()
     Af, iters, info = drivers.batched_mcl(mcl.DeviceCSC.from_host(A), comp)
     assert info["calls"] == iters.max()
+    assert info["not_converged"] == 0 and info["converged"].all()
+    lab, ncomp = mcl.components(Af)
+    lab = lab.cpu().numpy().astype(np.int64)
+    nclusters = 0
     for c in range(len(U.comp_ptr) - 1):
         c0, c1 = int(U.comp_ptr[c]), int(U.comp_ptr[c + 1])
-        blk = mcl.DeviceCSC.from_host(drivers.component_block(A, c0, c1))
-        Bf, it = drivers.component_mcl(blk)
+        blk_h = drivers.component_block(A, c0, c1)
+        Bf, it, conv = drivers.component_mcl(mcl.DeviceCSC.from_host(blk_h))
+        assert conv
         assert it == iters[c], c
         assert drivers.same_block(Af, c0, c1, Bf), c
-    # clusters of the batched result are the oracle's clusters of the same matrix
-    lab = oracle.clusters(Af.to_host())
-    assert len(lab) == A.ncols
+        # the batched result clusters every component as the oracle's MCL
+        # of that component alone does (labels offset by the block start)
+        _, it_o, lab_o = oracle.mcl(blk_h, normalized=True)
+        assert abs(it_o - it) <= 1, c
+        assert np.array_equal(lab[c0:c1], lab_o + c0), c
+        nclusters += len(np.unique(lab_o))
+    assert ncomp == nclusters
 
 
 def test_summa_merge_large_columns(drv):

@@ -446,3 +446,55 @@ def test_multipass_columns_expand_and_exact_path(mcl):
     ref, _, _ = mcl.iterate(dA)
     Y, _, st3 = mcl.iterate(dA, est_scale=0.5)
     assert torch.equal(Y.rowidx, ref.rowidx) and torch.equal(Y.val, ref.val)
+
+
+def _hub_graph(n=30000, hubs=300, hub_len=400, seed=81):
+    """Column `hubs` references every hub column 0..hubs-1 and each hub holds
+    hub_len random rows, so product column `hubs` has ~29,000 distinct rows:
+    more than the multi-pass LDS kernel holds (21,296 keys).  Other columns
+    hold their own row and two random rows."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    r, c = [], []
+    for k in range(hubs):
+        rr = rng.choice(n, size=hub_len, replace=False)
+        r.append(rr)
+        c.append(np.full(hub_len, k))
+    r.append(np.arange(hubs))
+    c.append(np.full(hubs, hubs))
+    rest = np.arange(hubs + 1, n)
+    r += [rest, rng.integers(0, n, rest.size), rng.integers(0, n, rest.size)]
+    c += [rest, rest, rest]
+    r, c = np.concatenate(r), np.concatenate(c)
+    M = sp.csc_matrix((rng.uniform(0.5, 1.0, r.size), (r, c)), shape=(n, n))
+    M.sum_duplicates()
+    M.sort_indices()
+    return oracle.normalize(CSC.from_scipy(M))
+
+
+def test_overflow_resolves_for_any_estimate(mcl):
+    """Estimates far too small (est_scale 1e-9, an untrained MLP) make the
+    largest product column overflow every LDS table; it is then sized by its
+    exact count and the result is still the oracle's."""
+    A = _hub_graph()
+    C, flops, nnz = oracle.expand(A, A)
+    assert nnz.max() > 21296
+    dA = up(mcl, A)
+    _, packed = mcl.mlp_init(11)          # untrained network
+    for kw in (dict(est_scale=1e-9), dict(estimator=mcl.EST_MLP, mlp_weights=packed),
+               dict(estimator=mcl.EST_MLP, mlp_weights=packed, est_scale=1e-9)):
+        print("sizing", {k: v for k, v in kw.items() if k != "mlp_weights"}, flush=True)
+        G, st = mcl.expand(dA, dA, **kw)
+        assert_same_matrix(G.to_host(), C, exact=True)
+        _, _, st2 = check_iterate(mcl, A, **kw)
+        if kw.get("est_scale") == 1e-9:
+            assert st["n_overflow"] > 0 and st2["n_overflow"] > 0
+
+
+def test_phased_iterate_matches_oracle(mcl):
+    """Phases (column ranges with their own temp storage) against the oracle,
+    not only against the unphased GPU run."""
+    A = oracle.normalize(planted_graph(8000, 250, s_cap=900, seed=25))
+    for pb in (3 << 20, 400 << 10):
+        _, _, st = check_iterate(mcl, A, phase_bytes=pb)
+        assert st["n_phases"] > 1

@@ -267,7 +267,7 @@ def test_cohen_exact_when_reaching_all_rows_is_unbiased_on_planted():
     assert abs(np.median(est[big] / nnz[big]) - 1.0) < 0.08
 
 
-# ---------------------------------------------------------------- merging (Section 5)
+# ---------------------------------------------------------------- merging (Section 4)
 
 def test_alg2_schedule_matches_hand_trace():
     rows = np.loadtxt(os.path.join(GOLDEN, "alg2_schedule_8.txt"), dtype=np.int64)
@@ -315,3 +315,48 @@ def test_merge_heap_sums_in_list_order():
     c = CSC(4, 1, np.array([0, 1], np.int64), np.array([0], np.int32), np.array([-1e16]))
     m = oracle.merge([a, b, c])
     assert m.val[0] == (1e16 + 1.0) + -1e16
+
+
+# ---------------------------------------------------------------- change between iterates
+
+def _csc_cols(nrows, cols):
+    """CSC from a list of {row: value} dicts (one per column)."""
+    colptr = [0]
+    rows, vals = [], []
+    for c in cols:
+        for r in sorted(c):
+            rows.append(r)
+            vals.append(c[r])
+        colptr.append(len(rows))
+    return CSC(nrows, len(cols), np.array(colptr, np.int64), np.array(rows, np.int32),
+               np.array(vals, np.float64))
+
+
+def test_delta_hand_worked_union_of_patterns():
+    """Alg. 1 loops while the iterate changes; the change is the largest
+    |a_new - a_old| over the union of both patterns (an entry present on one
+    side only counts with its full value).  Dyadic values make every
+    difference exact."""
+    old = _csc_cols(6, [
+        {0: 0.5, 2: 0.5},            # max on an old-only entry (row 2): 0.5
+        {0: 0.875, 1: 0.125},        # max on a new-only entry (row 3): 0.375
+        {1: 0.5, 2: 0.5},            # disjoint patterns: 0.75
+        {4: 0.25, 5: 0.75},          # identical: 0
+        {},                          # empty old column, new has one entry: 1
+        {3: 1.0},                    # new column empty: 1
+        {0: 0.25, 1: 0.25, 2: 0.5},  # max on a shared entry: 0.25
+    ])
+    new = _csc_cols(6, [
+        {0: 0.625, 1: 0.375},
+        {0: 0.5625, 1: 0.0625, 3: 0.375},
+        {0: 0.25, 3: 0.75},
+        {4: 0.25, 5: 0.75},
+        {5: 1.0},
+        {},
+        {0: 0.5, 1: 0.125, 2: 0.375},
+    ])
+    want = np.array([0.5, 0.375, 0.75, 0.0, 1.0, 1.0, 0.25])
+    got = oracle.delta(old, new)
+    assert np.array_equal(got, want), (got, want)
+    # the change is symmetric in its two arguments
+    assert np.array_equal(oracle.delta(new, old), want)

@@ -87,3 +87,47 @@ def test_training_reduces_loss():
         loss, g, _ = mlp.forward_backward(p, X, y)
         p, m, v = mlp.adam(p, m, v, g, t, 3e-3)
     assert loss < 0.05 * l0
+
+
+def test_adam_second_step_closed_form():
+    """Adam's bias-corrected moments after two steps: m2 = 0.09 g1 + 0.1 g2,
+    v2 = 0.000999 g1^2 + 0.001 g2^2, divided by 1 - 0.9^2 = 0.19 and
+    1 - 0.999^2 = 0.001999.  Constant gradients move every step by lr;
+    g = (1, -1) gives m_hat = -1/19 and v_hat = 1 at step 2."""
+    lr, eps = 0.01, 1e-8
+    p0 = np.zeros(2)
+    m0 = np.zeros(2)
+    v0 = np.zeros(2)
+    g1 = np.array([1.0, 1.0])
+    g2 = np.array([1.0, -1.0])
+    p1, m1, v1 = mlp.adam(p0, m0, v0, g1, 1, lr)
+    p2, m2, v2 = mlp.adam(p1, m1, v1, g2, 2, lr)
+    assert np.allclose(m2, [0.19, -0.01], rtol=1e-14)
+    assert np.allclose(v2, [0.001999, 0.001999], rtol=1e-14)
+    step1 = lr / (1.0 + eps)
+    want = np.array([-step1 - step1, -step1 + (lr / 19.0) / (1.0 + eps)])
+    assert np.allclose(p2, want, rtol=1e-12, atol=0)
+
+
+def test_features_hand_worked():
+    """The 12 inputs of the learned estimator on a 3-column example worked by
+    hand.  A (5 x 4): column 0 = rows {0, 2}, column 1 = rows {1, 3, 4},
+    column 2 empty, column 3 = row {4}.  B (4 x 3): column 0 references
+    k = 0, 1 with b = 0.5, 0.25; column 1 references only the empty k = 2
+    with b = 1; column 2 references k = 0, 1, 3 with b = 0.125, 0.5, 0.25."""
+    Acp = np.array([0, 2, 5, 5, 6])
+    Ari = np.array([0, 2, 1, 3, 4, 4])
+    Bcp = np.array([0, 2, 3, 6])
+    Bri = np.array([0, 1, 2, 0, 1, 3])
+    Bv = np.array([0.5, 0.25, 1.0, 0.125, 0.5, 0.25])
+    F = mlp.features(Acp, Ari, Bcp, Bri, Bv, 3, prev_nnz=np.array([7, 0, 11]))
+    L = np.log1p
+    want = np.array([
+        # nnz(B_j) flops  max   mean    min  it span  bmax  sum b^2   std of nnz(A_k)  prev   sum b*nnz(A_k)
+        [L(2), L(5), L(3), L(2.5), L(2), 3, L(5), 0.5, 0.3125, L(0.5), L(7), L(1.75)],
+        [L(1), L(0), L(0), L(0), L(0), 3, L(0), 1.0, 1.0, L(0), L(0), L(0)],
+        [L(3), L(6), L(3), L(2), L(1), 3, L(5), 0.5, 0.328125, L(np.sqrt(2.0 / 3.0)), L(11), L(2.0)],
+    ])
+    assert np.allclose(F, want, rtol=1e-15, atol=0), F - want
+    # without a previous iteration the tenth input is 0
+    assert np.all(mlp.features(Acp, Ari, Bcp, Bri, Bv, 0)[:, 10] == 0.0)
