@@ -184,6 +184,23 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
 int mcl_components(const mcl_csc *A, int32_t *labels, int64_t *ncomp, const mcl_allocator *alloc,
                    void *stream);
 
+/* mcl_components for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same matrix, labels and errors as mcl_components, with no allocator: the
+ * union-find parent array and the root counter live in a fixed scratch array
+ * inside the library (a 256-byte header plus MCL_NOALLOC_MAX_VERTICES int32,
+ * 16 MiB), one copy per GPU, held until the process ends.  The call
+ * allocates nothing on the device.  A square A with more than
+ * MCL_NOALLOC_MAX_VERTICES columns is rejected with MCL_EINVAL.  `stream`
+ * must belong to the current device.  ncomp (host, nullable): when NULL the
+ * call neither copies back nor synchronises, so it returns as soon as its
+ * kernels are enqueued.  Every call on one GPU uses that GPU's one scratch
+ * array, which keeps the last call's contents (each call re-initialises what
+ * it reads): calls that overlap on one GPU (other host threads, other
+ * streams) race and their labels are undefined. */
+#define MCL_NOALLOC_MAX_VERTICES (1 << 22)
+int mcl_components_noalloc(const mcl_csc *A, int32_t *labels, int64_t *ncomp, void *stream);
+
 /* Sparse SUMMA merge (Section 2 "Overview of Sparse SUMMA", Section 4):
  * C = sum of nparts same-shape matrices (`parts` is a HOST array of
  * descriptors whose arrays are device pointers).  Equal rows are summed in

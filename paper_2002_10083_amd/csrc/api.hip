@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -657,6 +658,44 @@ void fill_stats_totals(Mem &mem, int64_t n, const int64_t *nnz_prod, const int8_
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of mcl_components_noalloc: a 256-byte header (the root counter),
+// then the union-find parent array of up to MCL_NOALLOC_MAX_VERTICES
+// vertices.  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: host code uses only the per-device address that
+// hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_HEADER_BYTES = 256;
+constexpr size_t NOALLOC_SCRATCH_BYTES =
+    NOALLOC_HEADER_BYTES + sizeof(int32_t) * (size_t)MCL_NOALLOC_MAX_VERTICES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current and kept for the life of the process.
+unsigned char *scratch_on_current_device()
+{
+    int d = -1;
+    HIPC(hipGetDevice(&d));
+    if (d < 0 || d >= NOALLOC_MAX_DEVICES) fail(MCL_EHIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[d]) {
+        void *ptr = nullptr;
+        HIPC(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) fail(MCL_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch_dev[d] = ptr;
+    }
+    return (unsigned char *)g_scratch_dev[d];
+}
+
+}  // namespace
+
 // ===========================================================================
 // exported C ABI
 // ===========================================================================
@@ -1111,7 +1150,6 @@ int mcl_components(const mcl_csc *A, int32_t *labels, int64_t *ncomp, const mcl_
         if (n > 0) {
             int32_t *parent = mem.ws<int32_t>(n);
             int64_t *cnt = mem.ws<int64_t>(1);
-            HIPC(hipMemsetAsync(cnt, 0, sizeof(int64_t), mem.st));
             mcl::launch_components(dev(*A), parent, labels, cnt, mem.st);
             HIPC(hipGetLastError());
             HIPC(hipMemcpyAsync(&roots, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
@@ -1119,6 +1157,38 @@ int mcl_components(const mcl_csc *A, int32_t *labels, int64_t *ncomp, const mcl_
         HIPC(hipStreamSynchronize(mem.st));
         if (ncomp) *ncomp = roots;
     });
+}
+
+int mcl_components_noalloc(const mcl_csc *A, int32_t *labels, int64_t *ncomp, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    int rc = guarded([&] {
+        check_csc(A, "A");
+        if (A->nrows != A->ncols) fail(MCL_EINVAL, "mcl_components_noalloc needs a square matrix");
+        const int64_t n = A->ncols;
+        if (n > (int64_t)MCL_NOALLOC_MAX_VERTICES)
+            fail(MCL_EINVAL, "mcl_components_noalloc: " + std::to_string(n) +
+                                 " vertices exceed the scratch limit of " +
+                                 std::to_string((int64_t)MCL_NOALLOC_MAX_VERTICES));
+        if (n > 0 && !labels) fail(MCL_EINVAL, "labels is NULL");
+        if (n == 0) {
+            if (ncomp) *ncomp = 0;
+            return;
+        }
+        unsigned char *base = scratch_on_current_device();
+        int64_t *cnt = (int64_t *)base;
+        int32_t *parent = (int32_t *)(base + NOALLOC_HEADER_BYTES);
+        mcl::launch_components(dev(*A), parent, labels, cnt, st);
+        HIPC(hipGetLastError());
+        if (ncomp) {
+            int64_t roots = 0;
+            HIPC(hipMemcpyAsync(&roots, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            *ncomp = roots;
+        }
+    });
+    if (rc != MCL_OK) (void)hipStreamSynchronize(st);
+    return rc;
 }
 
 size_t mcl_mlp_packed_bytes(void) { return mcl::mlp_packed_bytes(); }

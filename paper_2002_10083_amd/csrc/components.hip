@@ -52,8 +52,12 @@ __device__ __forceinline__ void unite(int32_t *parent, int32_t a, int32_t b)
     }
 }
 
-__global__ __launch_bounds__(256) void k_cc_init(int64_t n, int32_t *__restrict__ parent)
+// Every vertex starts as its own root; the root counter is cleared here (a
+// kernel, not a memset, so the whole sequence can be recorded in a graph).
+__global__ __launch_bounds__(256) void k_cc_init(int64_t n, int32_t *__restrict__ parent,
+                                                 unsigned long long *__restrict__ nroots)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nroots = 0ull;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         parent[v] = (int32_t)v;
 }
@@ -92,7 +96,7 @@ void launch_components(const DevCSC &A, int32_t *parent, int32_t *label, int64_t
     const int64_t n = A.nrows;
     if (n <= 0) return;
     const unsigned gv = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, st, n, parent);
+    hipLaunchKernelGGL(k_cc_init, dim3(gv), dim3(256), 0, st, n, parent, (unsigned long long *)nroots);
     if (A.ncols > 0) {
         const unsigned gc = (unsigned)std::min<int64_t>((A.ncols + 3) / 4, 65536);
         hipLaunchKernelGGL(k_cc_hook, dim3(gc), dim3(256), 0, st, A, parent);

@@ -147,7 +147,8 @@ void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *
                        int32_t *hi, hipStream_t st);
 
 // ---- components.hip
-// weakly connected components of the pattern of a square A; label = smallest vertex id
+// weakly connected components of the pattern of a square A; label = smallest vertex id.
+// parent: int32[nrows] scratch; nroots: one int64, cleared by the first kernel.
 void launch_components(const DevCSC &A, int32_t *parent, int32_t *label, int64_t *nroots, hipStream_t st);
 
 // ---- mlp.hip

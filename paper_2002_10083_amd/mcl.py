@@ -108,6 +108,7 @@ _lib.mcl_estimate.argtypes = [ctypes.POINTER(_CSC), ctypes.POINTER(_CSC), ctypes
                               _P, _P, ctypes.POINTER(_Allocator), _P]
 _lib.mcl_components.argtypes = [ctypes.POINTER(_CSC), _P, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(_Allocator), _P]
+_lib.mcl_components_noalloc.argtypes = [ctypes.POINTER(_CSC), _P, ctypes.POINTER(ctypes.c_int64), _P]
 _lib.mcl_mlp_packed_bytes.restype = ctypes.c_size_t
 _lib.mcl_mlp_state_floats.restype = ctypes.c_size_t
 _lib.mcl_mlp_forward.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
@@ -117,7 +118,8 @@ _lib.mcl_mlp_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_flo
 
 #: every symbol include/mcl.h declares
 EXPORTS = ("mcl_default_params", "mcl_normalize", "mcl_expand", "mcl_prune", "mcl_inflate",
-           "mcl_iterate", "mcl_merge_partials", "mcl_components", "mcl_symbolic", "mcl_estimate",
+           "mcl_iterate", "mcl_merge_partials", "mcl_components", "mcl_components_noalloc",
+           "mcl_symbolic", "mcl_estimate",
            "mcl_mlp_packed_bytes", "mcl_mlp_forward", "mcl_mlp_state_floats", "mcl_mlp_init",
            "mcl_mlp_train_step", "mcl_last_error")
 
@@ -345,6 +347,25 @@ def components(A: DeviceCSC):
     _check(_lib.mcl_components(ctypes.byref(a), labels.data_ptr() if A.ncols else None,
                                ctypes.byref(nc), ctypes.byref(al.struct), _stream()))
     return labels, int(nc.value)
+
+
+#: largest vertex count mcl_components_noalloc accepts (its fixed scratch)
+NOALLOC_MAX_VERTICES = 1 << 22
+
+
+def components_noalloc(A: DeviceCSC, labels=None, sync: bool = True):
+    """mcl_components_noalloc: the same labels as components(), computed in the
+    library's fixed per-GPU scratch (no device allocation by the library).
+    `labels` may be a caller-provided device int32 tensor of A.ncols entries.
+    Returns (labels, ncomp); ncomp is None when sync is False (the call then
+    only enqueues its kernels)."""
+    if labels is None:
+        labels = torch.empty(A.ncols, dtype=torch.int32, device="cuda")
+    nc = ctypes.c_int64(0)
+    a = A._c()
+    _check(_lib.mcl_components_noalloc(ctypes.byref(a), labels.data_ptr() if A.ncols else None,
+                                       ctypes.byref(nc) if sync else None, _stream()))
+    return labels, (int(nc.value) if sync else None)
 
 
 def symbolic(A: DeviceCSC, B: DeviceCSC, exact: bool = False):
