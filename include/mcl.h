@@ -118,6 +118,12 @@ typedef struct {
     int64_t bin_bnnz[8];
     int64_t bin_out[8];
     int64_t n_phases;         /* column phases used by mcl_iterate (see mcl_params.phase_bytes) */
+    /* bins whose columns are split over several workgroups (an accumulation
+       kernel, then a kernel that sorts each column and runs the epilogue):
+       time of the accumulation kernel alone (0 for other bins), and the
+       unpruned product entries of every bin's columns */
+    double bin_part_ms[8];
+    int64_t bin_prod[8];
 } mcl_stats;
 
 /* Fills `p` with the defaults: theta 1e-4, S 1100, R 1400, pct 0.9, r 2,

@@ -244,8 +244,9 @@ struct EngineOut {
     int64_t n_overflow = 0, n_global = 0;
     double t_numeric = 0, t_fallback = 0;
     double bin_ms[8] = {0};
+    double bin_part_ms[8] = {0};  // split bins: accumulation kernel alone
     int64_t bin_cols[8] = {0};
-    int64_t bin_acc[24] = {0};  // per bin: flops, nnz(B_*j), output entries
+    int64_t bin_acc[32] = {0};  // per bin: flops, nnz(B_*j), output entries, unpruned entries
     int n_phases = 0;
 };
 
@@ -265,21 +266,28 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
     int32_t off = 0;
     std::vector<hipEvent_t> ev;
     std::vector<int> evbin;
+    std::vector<hipEvent_t> evmid;  // per timed bin: between the kernels of a split launch (or null)
     for (int b = 0; b < 8; ++b) {
         const int32_t c = counts[b];
         if (c > 0) {
             a.cols = lists + off;
             a.ncols = c;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
+            hipEvent_t e0 = nullptr, e1 = nullptr, em = nullptr;
+            int variant = 0;
+            if (b < mcl::NUM_LDS_BINS) {
+                variant = (int)((policy >> (4 * b)) & 15u);
+                if (variant >= mcl::lds_bin_variants(b)) variant = 0;
+            }
             if (timed) {
                 HIPC(hipEventCreate(&e0));
                 HIPC(hipEventCreate(&e1));
+                if (b < mcl::NUM_LDS_BINS && mcl::lds_variant_split(b, variant) && a.part_cnt &&
+                    mode != mcl::MODE_COUNT && !a.parts)
+                    HIPC(hipEventCreate(&em));
                 HIPC(hipEventRecord(e0, mem.st));
             }
             if (b < mcl::NUM_LDS_BINS) {
-                int variant = (int)((policy >> (4 * b)) & 15u);
-                if (variant >= mcl::lds_bin_variants(b)) variant = 0;
-                mcl::launch_numeric_lds(b, variant, mode, a, mem.st);
+                mcl::launch_numeric_lds(b, variant, mode, a, mem.st, em);
             } else {
                 // multi-pass LDS kernel for the columns within its capacity,
                 // HBM-resident tables for the rest
@@ -306,6 +314,7 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
                 ev.push_back(e0);
                 ev.push_back(e1);
                 evbin.push_back(b);
+                evmid.push_back(em);
             }
             eo.bin_cols[b] += c;
         }
@@ -317,9 +326,16 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
             float t = 0.f;
             (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
             eo.bin_ms[evbin[i]] += t;
+            if (evmid[i]) {
+                float tp = 0.f;
+                (void)hipEventElapsedTime(&tp, ev[2 * i], evmid[i]);
+                eo.bin_part_ms[evbin[i]] += tp;
+            }
         }
     }
     for (auto e : ev) (void)hipEventDestroy(e);
+    for (auto e : evmid)
+        if (e) (void)hipEventDestroy(e);
 }
 
 // Column ranges of a phased product: consecutive columns whose planned temp
@@ -407,6 +423,8 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         HIPC(hipMemsetAsync(dummy, 0xFF, 8 * sizeof(int64_t), mem.st));  // row -1 (no row)
         a.dummy = dummy;
     }
+    a.part_cnt = mem.ws<int32_t>(std::max<int64_t>(n, 1));
+    HIPC(hipMemsetAsync(a.part_cnt, 0, std::max<int64_t>(n, 1) * sizeof(int32_t), mem.st));
     a.lo = pl.lo;
     a.hi = pl.hi;
     a.hbm_only = pl.hbm_only;
@@ -420,11 +438,12 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     run_bins(mem, mode, a, pl.counts, pl.lists, pl.max_global, eo, true, policy);
     // per-bin totals of the first pass (the launch shape the timing refers to)
     {
-        int64_t *acc = mem.ws<int64_t>(24);
-        HIPC(hipMemsetAsync(acc, 0, 24 * sizeof(int64_t), mem.st));
+        int64_t *acc = mem.ws<int64_t>(32);
+        HIPC(hipMemsetAsync(acc, 0, 32 * sizeof(int64_t), mem.st));
         mcl::BinOffsets cnt{};
         for (int b = 0; b < 8; ++b) cnt.off[b] = pl.counts[b];
-        mcl::launch_bin_sums(pl.lists, offsets_of(pl.counts), cnt, pl.flops, bcolptr, pl.cnt, acc, mem.st);
+        mcl::launch_bin_sums(pl.lists, offsets_of(pl.counts), cnt, pl.flops, bcolptr, pl.cnt, a.nnz_prod, acc,
+                             mem.st);
         HIPC(hipMemcpyAsync(eo.bin_acc, acc, sizeof(eo.bin_acc), hipMemcpyDeviceToHost, mem.st));
     }
     tm.mark();
@@ -526,9 +545,11 @@ void copy_bin_stats(const EngineOut &eo, mcl_stats *s)
     for (int b = 0; b < 8; ++b) {
         s->bin_cols[b] = eo.bin_cols[b];
         s->bin_ms[b] = eo.bin_ms[b];
-        s->bin_flops[b] = eo.bin_acc[3 * b];
-        s->bin_bnnz[b] = eo.bin_acc[3 * b + 1];
-        s->bin_out[b] = eo.bin_acc[3 * b + 2];
+        s->bin_flops[b] = eo.bin_acc[4 * b];
+        s->bin_bnnz[b] = eo.bin_acc[4 * b + 1];
+        s->bin_out[b] = eo.bin_acc[4 * b + 2];
+        s->bin_prod[b] = eo.bin_acc[4 * b + 3];
+        s->bin_part_ms[b] = eo.bin_part_ms[b];
     }
 }
 
@@ -888,9 +909,10 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
                 eo.t_fallback += e.t_fallback;
                 for (int b = 0; b < 8; ++b) {
                     eo.bin_ms[b] += e.bin_ms[b];
+                    eo.bin_part_ms[b] += e.bin_part_ms[b];
                     eo.bin_cols[b] += e.bin_cols[b];
                 }
-                for (int b = 0; b < 24; ++b) eo.bin_acc[b] += e.bin_acc[b];
+                for (int b = 0; b < 32; ++b) eo.bin_acc[b] += e.bin_acc[b];
             }
             eo.n_phases = (int)outs.size();
             if (comp_ptr) mcl::launch_counts_inactive(dA, col_comp, active, pl.cnt, delta, mem.st);

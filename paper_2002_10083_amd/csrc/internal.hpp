@@ -47,6 +47,7 @@ struct NumericArgs {
     const double *sval;       //   and values
     uint32_t src_end;         // sliced copy: index of the entry past the last (row -1, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
+    int32_t *part_cnt;        // split sliced kernels: keys appended per column (all zero between launches)
 };
 
 // ---- spgemm.hip
@@ -57,6 +58,7 @@ constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 sl
 int lds_bin_slots(int bin);                          // slots of bin
 int lds_bin_cap(int bin);                            // max distinct keys of bin
 bool lds_variant_sliced(int bin, int variant);       // launch reads the sliced layout of A
+bool lds_variant_split(int bin, int variant);        // split sliced tables (needs NumericArgs.part_cnt)
 // phase [c0, c1) of a phased product: bins (-1 outside), phase-relative temp offsets, bin counts
 // largest columns: multi-pass LDS accumulation + sort/epilogue in HBM scratch
 size_t mpass_slab_bytes();
@@ -101,15 +103,18 @@ void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
                  int32_t *exact_list, int32_t *n_exact, bool to_multipass, bool force_exact,
                  hipStream_t st);
+// acc: per bin {flops, nnz(B_*j), output entries, unpruned product entries (prod, or out_cnt if null)}
 void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
-                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
-                     hipStream_t st);
+                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt,
+                     const int64_t *prod, int64_t *acc, hipStream_t st);
 constexpr int MAX_REGIONS = 8;
 struct TempRegions {
     const int32_t *row[MAX_REGIONS];
     const double *val[MAX_REGIONS];
 };
-void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st);
+// mid (nullable): recorded between the accumulation and finishing kernels of a split launch
+void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,
+                        hipEvent_t mid = nullptr);
 int lds_bin_variants(int bin);
 void launch_numeric_global(NumericMode mode, const NumericArgs &a, int S, int cap, void *slab,
                            size_t slab_bytes, int nslabs, hipStream_t st);

@@ -657,32 +657,38 @@ __global__ __launch_bounds__(256) void k_bin_sums(const int32_t *__restrict__ li
                                                   BinOffsets cnt, const int64_t *__restrict__ flops,
                                                   const int64_t *__restrict__ bcolptr,
                                                   const int64_t *__restrict__ out_cnt,
+                                                  const int64_t *__restrict__ prod,
                                                   unsigned long long *__restrict__ acc)
 {
     const int b = blockIdx.y;
-    int64_t f = 0, bn = 0, o = 0;
+    int64_t f = 0, bn = 0, o = 0, pr = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt.off[b]; i += gridDim.x * blockDim.x) {
         const int j = lists[off.off[b] + i];
         f += flops[j];
         if (bcolptr) bn += bcolptr[j + 1] - bcolptr[j];
-        o += max(out_cnt[j], (int64_t)0);
+        const int64_t oc = max(out_cnt[j], (int64_t)0);
+        o += oc;
+        pr += (prod && out_cnt[j] >= 0) ? prod[j] : oc;
     }
     f = wave_sum_i64(f);
     bn = wave_sum_i64(bn);
     o = wave_sum_i64(o);
+    pr = wave_sum_i64(pr);
     if (lane() == 0) {
-        atomicAdd(&acc[3 * b + 0], (unsigned long long)f);
-        atomicAdd(&acc[3 * b + 1], (unsigned long long)bn);
-        atomicAdd(&acc[3 * b + 2], (unsigned long long)o);
+        atomicAdd(&acc[4 * b + 0], (unsigned long long)f);
+        atomicAdd(&acc[4 * b + 1], (unsigned long long)bn);
+        atomicAdd(&acc[4 * b + 2], (unsigned long long)o);
+        atomicAdd(&acc[4 * b + 3], (unsigned long long)pr);
     }
 }
 
 void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
-                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt, int64_t *acc,
+                     const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt,
+                     const int64_t *prod, int64_t *acc,
                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_bin_sums, dim3(64, 8), dim3(256), 0, st, lists, off, cnt, flops, bcolptr, out_cnt,
-                       (unsigned long long *)acc);
+                       prod, (unsigned long long *)acc);
 }
 
 __global__ __launch_bounds__(256) void k_scatter_bins(int64_t ncols, const int32_t *__restrict__ bin,
@@ -1731,6 +1737,188 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Split sliced tables: the row groups of a column are divided among P
+// workgroups ("parts") of NWP waves, which run concurrently and hold only
+// their own waves' tables (NWP * SW slots, no epilogue arrays), so several
+// parts fit on one CU.  Part p covers the groups [p*NG/P, (p+1)*NG/P); as in
+// the one-workgroup kernel every row belongs to exactly one wave, which adds
+// its products in ascending k.  A part appends its keys and values, unsorted,
+// to the column's temp slot at an offset taken from the column's counter
+// part_cnt[j]; PART_OVF in that counter marks a column that overflowed.
+// k_finish_part then sorts each column by row and runs the epilogue, and
+// resets the counter.  The block index keeps the P parts of a column on one
+// XCD (workgroups are dealt to the 8 XCDs in turn), so the column's step
+// metadata is fetched once per L2.
+// ---------------------------------------------------------------------------
+constexpr int32_t PART_OVF = 1 << 30;
+
+template <int NWP, int SW, int P, int MODE, int D>
+__device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
+{
+    constexpr int G = NG / (P * NWP);  // groups per wave
+    constexpr int CAPW = (13 * SW) / 16;
+    static_assert(NG % (P * NWP) == 0, "groups must divide evenly");
+    struct alignas(16) Sh {
+        double val[NWP * SW];
+        int32_t key[NWP * SW];
+        int32_t wcnt[NWP], wovf[NWP];
+        int32_t misc[4];
+        double dmisc[4];
+    };
+    __shared__ Sh sh __attribute__((aligned(16)));
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    const uint32_t b = blockIdx.x;
+    const uint32_t r = b % (8 * P);
+    const int p = (int)(r / 8);
+    const uint32_t idx = (b / (8 * P)) * 8 + r % 8;
+    if (idx >= (uint32_t)a.ncols) return;  // whole workgroup
+    const int64_t j = a.cols[idx];
+    if (tid == 0) sh.misc[0] = 0;
+    __syncthreads();
+    const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
+    const int g0 = p * (NG / P) + w * G;
+    const int keys_w = slice_accumulate<SW, MODE, D>(a, j, g0, g0 + G, sh.key + w * SW, sh.val + w * SW,
+                                                     &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[0], col_cap);
+    if (lane() == 0) {
+        sh.wcnt[w] = keys_w;
+        if (keys_w > CAPW) sh.wovf[w] = 1;
+    }
+    __syncthreads();
+    int mp = 0, ovf = 0, pre = 0;
+    for (int q = 0; q < NWP; ++q) {
+        if (q < w) pre += sh.wcnt[q];
+        mp += sh.wcnt[q];
+        ovf |= sh.wovf[q];
+    }
+    if (tid == 0) {
+        int off = -1;
+        if (!ovf) {
+            off = atomicAdd(&a.part_cnt[j], mp);
+            if ((off & PART_OVF) || (int64_t)off + mp > col_cap) ovf = 1;
+        }
+        if (ovf) {
+            atomicOr(&a.part_cnt[j], PART_OVF);
+            off = -1;
+        }
+        sh.misc[1] = off;
+    }
+    __syncthreads();
+    const int off = sh.misc[1];
+    if (off < 0) return;
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    const int32_t *wkey = sh.key + w * SW;
+    const double *wval = sh.val + w * SW;
+    int run = 0;
+    for (int s0 = 0; s0 < SW; s0 += WAVE) {
+        const int k = wkey[s0 + lane()];
+        const uint64_t mk = ballot(k != EMPTY_KEY);
+        if (k != EMPTY_KEY) {
+            const int64_t d = base + off + pre + run + popc_below(mk);
+            a.out_row[d] = k;
+            a.out_val[d] = wval[s0 + lane()];
+        }
+        run += __popcll(mk);
+    }
+}
+
+// Two register budgets: the compiler's choice, and 64 VGPRs (eight waves
+// per SIMD when the LDS allows it).
+template <int NWP, int SW, int P, int MODE, int D>
+__global__ __launch_bounds__(NWP * WAVE) void k_numeric_part(NumericArgs a)
+{
+    numeric_part_body<NWP, SW, P, MODE, D>(a);
+}
+
+template <int NWP, int SW, int P, int MODE, int D>
+__global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) void k_numeric_part_v64(
+    NumericArgs a)
+{
+    numeric_part_body<NWP, SW, P, MODE, D>(a);
+}
+
+// Finishing kernel of the split sliced tables: one workgroup per column
+// loads the m appended entries into LDS, sorts them by row and writes them
+// (expand) or runs the fused epilogue (iterate).  CAPF bounds m (the largest
+// capacity of the bins that use the split kernels).
+template <int NT, int CAPF, int MODE>
+__global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a)
+{
+    constexpr int NBS = CAPF / 3;  // sort buckets
+    constexpr int NBLK = CAPF / WAVE + 2;
+    struct alignas(16) Sh {
+        double val[CAPF];
+        int32_t key[CAPF];
+        double p0[NBLK], p1[NBLK];
+        int32_t ip[NBLK];
+        int32_t bcnt[NBS], bcur[NBS];
+        int32_t hist[256];
+        uint16_t list[CAPF], sorted[CAPF];
+        int32_t misc[16];
+        double dmisc[4];
+        int32_t wsum[NT / WAVE];
+    };
+    __shared__ Sh sh __attribute__((aligned(16)));
+    const int tid = threadIdx.x;
+    const int64_t j = a.cols[blockIdx.x];
+    const int c = a.part_cnt[j];
+    __syncthreads();  // every thread has read the counter before it is reset
+    if (tid == 0) a.part_cnt[j] = 0;
+    if ((c & PART_OVF) || c > CAPF) {
+        if (tid == 0) a.out_cnt[j] = -1;
+        return;
+    }
+    const int m = c;
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    for (int q = tid; q < m; q += NT) {
+        sh.key[q] = a.out_row[base + q];
+        sh.val[q] = a.out_val[base + q];
+    }
+    __syncthreads();
+    const int32_t lo = a.lo[j];
+    const int64_t span = (int64_t)a.hi[j] - lo + 1;
+    if (MODE == MODE_EXPAND) {
+        sort_table<NT, false, uint16_t>(sh.key, m, m, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
+                                        [&](int rank, int s) {
+                                            a.out_row[base + rank] = sh.key[s];
+                                            a.out_val[base + rank] = sh.val[s];
+                                        });
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+    sort_table<NT, false, uint16_t>(sh.key, m, m, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
+                                    [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
+    __syncthreads();
+    Scratch<uint16_t> sc{sh.key, sh.val, sh.list, sh.sorted, sh.bcnt, sh.bcur, sh.p0, sh.p1,
+                         sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
+    const int64_t bs = a.B.colptr[j];
+    const int mj = (int)(a.B.colptr[j + 1] - bs);
+    iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, sh.key, sh.val, sc, [&](int32_t k) {
+        int l = 0, h = m;  // first rank with key >= k
+        while (l < h) {
+            const int mid = (l + h) >> 1;
+            if (sh.key[sh.sorted[mid]] < k) l = mid + 1;
+            else h = mid;
+        }
+        return (l < m && sh.key[sh.sorted[l]] == k) ? (int)sh.sorted[l] : -1;
+    });
+}
+
+template <int NWP, int SW, int P, int MODE, int D, int CAPF, int WPE>
+static void launch_part(const NumericArgs &a, hipStream_t st, hipEvent_t mid)
+{
+    constexpr int NTF = CAPF >= 6144 ? 1024 : CAPF >= 3072 ? 512 : 256;
+    const unsigned n = (unsigned)a.ncols;
+    const unsigned grid = ((n + 7) / 8) * 8 * P;
+    if constexpr (WPE == 8)
+        hipLaunchKernelGGL((k_numeric_part_v64<NWP, SW, P, MODE, D>), dim3(grid), dim3(NWP * WAVE), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_numeric_part<NWP, SW, P, MODE, D>), dim3(grid), dim3(NWP * WAVE), 0, st, a);
+    if (mid) (void)hipEventRecord(mid, st);
+    hipLaunchKernelGGL((k_finish_part<NTF, CAPF, MODE>), dim3(n), dim3(NTF), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
 // Columns too large for one LDS table set: P = 2 or 4 passes of 16 waves,
 // pass p covering the row groups [p*64/P, (p+1)*64/P) (disjoint row sets, so
 // every row is accumulated in exactly one pass, in ascending k).  Each pass
@@ -1899,16 +2087,19 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
 // mcl_params.bin_policy (4 bits per bin).  Merge and exact-count launches use
 // the shared-table shape (shared_table_variant).
 template <int MODE, bool IS_MERGE>
-static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStream_t st)
+static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStream_t st, hipEvent_t mid = nullptr)
 {
     const int n = a.ncols;
     if (n <= 0) return;
 #define MCL_LAUNCH(S_, NW_, CPW_, E_, D_, P_)                                               \
     hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE, P_>),          \
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
-#define MCL_SPLIT(NW_, D_)                                                                   \
+#define MCL_SPLIT_W(NW_, SW_, D_)                                                            \
     if constexpr (!IS_MERGE && MODE != MODE_COUNT)                                           \
-        hipLaunchKernelGGL((k_numeric_hsplit<NW_, 512, MODE, D_>), dim3(n), dim3(NW_ * WAVE), 0, st, a)
+        hipLaunchKernelGGL((k_numeric_hsplit<NW_, SW_, MODE, D_>), dim3(n), dim3(NW_ * WAVE), 0, st, a)
+#define MCL_SPLIT(NW_, D_) MCL_SPLIT_W(NW_, 512, D_)
+#define MCL_PART(NWP_, SW_, P_, D_, CAPF_, WPE_)                                             \
+    if constexpr (!IS_MERGE && MODE != MODE_COUNT) launch_part<NWP_, SW_, P_, MODE, D_, CAPF_, WPE_>(a, st, mid)
     switch (bin * 8 + variant) {
     case 0: MCL_LAUNCH(128, 1, 4, 2, 4, false); break;
     case 1: MCL_LAUNCH(128, 1, 4, 1, 8, false); break;
@@ -1920,30 +2111,56 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 25: MCL_LAUNCH(1024, 2, 1, 2, 4, false); break;
     case 26: MCL_LAUNCH(1024, 2, 1, 2, 4, true); break;
     case 27: MCL_LAUNCH(1024, 1, 2, 4, 4, false); break;
+    case 28: MCL_PART(1, 512, 2, 2, 768, 1); break;
+    case 29: MCL_PART(1, 512, 2, 2, 768, 8); break;
     case 32: MCL_SPLIT(4, 4); break;
     case 33: MCL_LAUNCH(2048, 4, 1, 2, 4, false); break;
     case 34: MCL_LAUNCH(2048, 4, 1, 2, 4, true); break;
     case 35: MCL_LAUNCH(2048, 4, 1, 1, 8, true); break;
+    case 36: MCL_PART(2, 512, 2, 2, 1536, 1); break;
+    case 37: MCL_PART(1, 512, 4, 2, 1536, 1); break;
+    case 38: MCL_PART(1, 512, 4, 2, 1536, 8); break;
     case 40: MCL_SPLIT(8, 4); break;
     case 41: MCL_LAUNCH(4096, 8, 1, 1, 4, false); break;
     case 42: MCL_LAUNCH(4096, 8, 1, 1, 4, true); break;
     case 43: MCL_SPLIT(8, 8); break;
     case 44: MCL_LAUNCH(4096, 8, 1, 1, 8, false); break;
+    case 45: MCL_PART(4, 512, 2, 2, 3072, 1); break;
+    case 46: MCL_PART(2, 512, 4, 2, 3072, 1); break;
+    case 47: MCL_PART(1, 512, 8, 2, 3072, 1); break;
     case 48: MCL_SPLIT(16, 4); break;
     case 49: MCL_LAUNCH(8192, 16, 1, 1, 4, false); break;
     case 50: MCL_LAUNCH(8192, 16, 1, 1, 4, true); break;
     case 51: MCL_LAUNCH(8192, 16, 1, 1, 8, true); break;
     case 52: MCL_LAUNCH(8192, 16, 1, 1, 8, false); break;
     case 53: MCL_SPLIT(16, 2); break;
+    case 54: MCL_PART(2, 512, 8, 2, 6144, 1); break;
+    case 55: MCL_PART(1, 512, 16, 2, 6144, 1); break;
+    case 56: MCL_PART(4, 512, 4, 2, 6144, 8); break;
+    case 57: MCL_PART(8, 512, 2, 2, 6144, 1); break;
+    case 58: MCL_PART(2, 512, 8, 2, 6144, 8); break;
+    case 59: MCL_PART(8, 512, 2, 2, 6144, 8); break;
+    case 60: MCL_PART(4, 512, 4, 2, 6144, 1); break;
+    case 61: MCL_PART(1, 512, 16, 2, 6144, 8); break;
+    case 62: MCL_PART(4, 512, 4, 1, 6144, 8); break;
     default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
     }
+#undef MCL_PART
 #undef MCL_SPLIT
+#undef MCL_SPLIT_W
 #undef MCL_LAUNCH
 }
 
 bool lds_variant_sliced(int bin, int variant)
 {
-    return (bin >= 3 && bin <= 6 && variant == 0) || (bin == 5 && variant == 3) || (bin == 6 && variant == 5);
+    return (bin >= 3 && bin <= 6 && variant == 0) || (bin == 5 && variant == 3) || lds_variant_split(bin, variant) ||
+           (bin == 6 && variant == 5);
+}
+
+bool lds_variant_split(int bin, int variant)
+{
+    return (bin == 3 && variant >= 4) || (bin == 4 && variant >= 4) || (bin == 5 && variant >= 5) ||
+           (bin == 6 && variant >= 6);
 }
 
 // Launch used by merges and exact counts (modes the sliced kernels do not
@@ -1952,21 +2169,23 @@ static int shared_table_variant(int bin) { return (bin >= 3 && bin <= 6) ? 1 : 0
 
 int lds_bin_variants(int bin)
 {
-    static const int nv[NUM_LDS_BINS] = {2, 2, 2, 4, 4, 5, 6};
+    static const int nv[NUM_LDS_BINS] = {2, 2, 2, 6, 7, 8, 15};
     return (bin >= 0 && bin < NUM_LDS_BINS) ? nv[bin] : 1;
 }
 
-void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st)
+void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,
+                        hipEvent_t mid)
 {
     if (a.parts) {
         launch_lds_mode<MODE_EXPAND, true>(bin, shared_table_variant(bin), a, st);
         return;
     }
+    if (lds_variant_split(bin, variant) && !a.part_cnt) variant = 0;
     if (lds_variant_sliced(bin, variant) && !a.goff) variant = shared_table_variant(bin);
     switch (mode) {
     case MODE_COUNT: launch_lds_mode<MODE_COUNT, false>(bin, shared_table_variant(bin), a, st); break;
-    case MODE_EXPAND: launch_lds_mode<MODE_EXPAND, false>(bin, variant, a, st); break;
-    case MODE_ITERATE: launch_lds_mode<MODE_ITERATE, false>(bin, variant, a, st); break;
+    case MODE_EXPAND: launch_lds_mode<MODE_EXPAND, false>(bin, variant, a, st, mid); break;
+    case MODE_ITERATE: launch_lds_mode<MODE_ITERATE, false>(bin, variant, a, st, mid); break;
     }
 }
 

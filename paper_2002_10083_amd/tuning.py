@@ -18,7 +18,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-VARIANTS = [2, 2, 2, 4, 4, 5, 6]        # launch variants per LDS bin
+VARIANTS = [2, 2, 2, 6, 7, 8, 15]       # launch variants per LDS bin
 SCALES = (1.0, 1.25, 1.6)
 KEYS = (5, 8, 12)                       # Cohen keys per vertex
 
