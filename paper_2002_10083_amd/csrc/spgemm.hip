@@ -1752,7 +1752,11 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
 // ---------------------------------------------------------------------------
 constexpr int32_t PART_OVF = 1 << 30;
 
-template <int NWP, int SW, int P, int MODE, int D>
+__device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j);
+
+// MP: the launch holds the multi-pass columns of the largest bin together
+// with HBM-table columns, which it skips.
+template <int NWP, int SW, int P, int MODE, int D, bool MP = false>
 __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
 {
     constexpr int G = NG / (P * NWP);  // groups per wave
@@ -1774,6 +1778,7 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
     const uint32_t idx = (b / (8 * P)) * 8 + r % 8;
     if (idx >= (uint32_t)a.ncols) return;  // whole workgroup
     const int64_t j = a.cols[idx];
+    if (MP && !multipass_column(a, j)) return;  // whole workgroup
     if (tid == 0) sh.misc[0] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
@@ -1830,6 +1835,15 @@ __global__ __launch_bounds__(NWP * WAVE) void k_numeric_part(NumericArgs a)
     numeric_part_body<NWP, SW, P, MODE, D>(a);
 }
 
+// the multi-pass columns of the largest bin: 64 waves per column, one row group each
+constexpr int MPP_NW = 8, MPP_P = 8;
+static_assert(MPP_NW * MPP_P == NG, "one group per wave");
+template <int MODE>
+__global__ __launch_bounds__(MPP_NW * WAVE) void k_numeric_mpart(NumericArgs a)
+{
+    numeric_part_body<MPP_NW, 512, MPP_P, MODE, 2, true>(a);
+}
+
 template <int NWP, int SW, int P, int MODE, int D>
 __global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) void k_numeric_part_v64(
     NumericArgs a)
@@ -1839,10 +1853,14 @@ __global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) vo
 
 // Finishing kernel of the split sliced tables: one workgroup per column
 // loads the m appended entries into LDS, sorts them by row and writes them
-// (expand) or runs the fused epilogue (iterate).  CAPF bounds m (the largest
-// capacity of the bins that use the split kernels).
+// (expand) or runs the fused epilogue (iterate).  Several launches of
+// different sizes share a bin's columns: this one takes the columns with
+// mlo < m <= mhi (CAPF >= mhi bounds its LDS arrays), and the last one also
+// the columns that overflowed.  A column is finished by exactly one launch,
+// which resets its counter to 0 (a value only the first launch takes, with
+// mlo < 0).
 template <int NT, int CAPF, int MODE>
-__global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a)
+__global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int mhi, int last)
 {
     constexpr int NBS = CAPF / 3;  // sort buckets
     constexpr int NBLK = CAPF / WAVE + 2;
@@ -1862,9 +1880,11 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a)
     const int tid = threadIdx.x;
     const int64_t j = a.cols[blockIdx.x];
     const int c = a.part_cnt[j];
+    const bool bad = (c & PART_OVF) || c > mhi;
+    if (bad ? !last : (c <= mlo || c > mhi)) return;  // another launch's column (whole workgroup)
     __syncthreads();  // every thread has read the counter before it is reset
     if (tid == 0) a.part_cnt[j] = 0;
-    if ((c & PART_OVF) || c > CAPF) {
+    if (bad) {
         if (tid == 0) a.out_cnt[j] = -1;
         return;
     }
@@ -1915,7 +1935,19 @@ static void launch_part(const NumericArgs &a, hipStream_t st, hipEvent_t mid)
     else
         hipLaunchKernelGGL((k_numeric_part<NWP, SW, P, MODE, D>), dim3(grid), dim3(NWP * WAVE), 0, st, a);
     if (mid) (void)hipEventRecord(mid, st);
-    hipLaunchKernelGGL((k_finish_part<NTF, CAPF, MODE>), dim3(n), dim3(NTF), 0, st, a);
+    // finishing launches by column size: smaller columns get smaller
+    // workgroups, several of which share a CU
+    if constexpr (CAPF >= 6144) {
+        hipLaunchKernelGGL((k_finish_part<256, 2048, MODE>), dim3(n), dim3(256), 0, st, a, -1, 2048, 0);
+        hipLaunchKernelGGL((k_finish_part<512, 4096, MODE>), dim3(n), dim3(512), 0, st, a, 2048, 4096, 0);
+        hipLaunchKernelGGL((k_finish_part<NTF, CAPF, MODE>), dim3(n), dim3(NTF), 0, st, a, 4096, CAPF, 1);
+    } else if constexpr (CAPF >= 3072) {
+        hipLaunchKernelGGL((k_finish_part<256, 1024, MODE>), dim3(n), dim3(256), 0, st, a, -1, 1024, 0);
+        hipLaunchKernelGGL((k_finish_part<256, 2048, MODE>), dim3(n), dim3(256), 0, st, a, 1024, 2048, 0);
+        hipLaunchKernelGGL((k_finish_part<NTF, CAPF, MODE>), dim3(n), dim3(NTF), 0, st, a, 2048, CAPF, 1);
+    } else {
+        hipLaunchKernelGGL((k_finish_part<NTF, CAPF, MODE>), dim3(n), dim3(NTF), 0, st, a, -1, CAPF, 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1997,7 +2029,9 @@ __global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
 // to HBM scratch, sorts them by row, then writes them (expand) or runs the
 // fused epilogue on them (iterate).  Persistent workgroups with one scratch
 // slab each, like the HBM-table kernel.
-template <int MODE>
+// SPLIT: the entries were appended by k_numeric_mpart (count and overflow
+// flag in part_cnt, reset here) instead of k_numeric_mpass (count in out_cnt).
+template <int MODE, bool SPLIT>
 __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab, size_t slab_bytes)
 {
     constexpr int NT = 1024;
@@ -2022,8 +2056,21 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
     const int tid = threadIdx.x;
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
         const int64_t j = a.cols[idx];
-        if (!multipass_column(a, j) || a.out_cnt[j] < 0) continue;
-        const int m = (int)a.out_cnt[j];
+        if (!multipass_column(a, j)) continue;
+        int m;
+        if constexpr (SPLIT) {
+            const int c = a.part_cnt[j];
+            __syncthreads();  // every thread has read the counter before it is reset
+            if (tid == 0) a.part_cnt[j] = 0;
+            if ((c & PART_OVF) || c > (int)MP_MAX) {
+                if (tid == 0) a.out_cnt[j] = -1;
+                continue;
+            }
+            m = c;
+        } else {
+            if (a.out_cnt[j] < 0) continue;
+            m = (int)a.out_cnt[j];
+        }
         const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
         for (int q = tid; q < m; q += NT) {
             skey[q] = a.out_row[base + q];
@@ -2037,6 +2084,7 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
                 a.out_row[base + rank] = skey[s];
                 a.out_val[base + rank] = sval[s];
             });
+            if (SPLIT && tid == 0) a.out_cnt[j] = m;
         } else {
             sort_table<NT, true, int32_t>(skey, m, m, lo, span, bcnt, bcur, NB, list, wsum,
                                           [&](int rank, int s) { sorted[rank] = s; });
@@ -2068,14 +2116,28 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
 {
     if (a.ncols <= 0 || !a.goff || a.parts || mode == MODE_COUNT) return;
     const int grid = std::min(nslabs, a.ncols);
+    const unsigned pgrid = (unsigned)(((a.ncols + 7) / 8) * 8 * MPP_P);
+    const bool split = a.part_cnt != nullptr;
     if (mode == MODE_EXPAND) {
-        hipLaunchKernelGGL(k_numeric_mpass<MODE_EXPAND>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
-        hipLaunchKernelGGL(k_finish_mpass<MODE_EXPAND>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
-                           slab_bytes);
+        if (split) {
+            hipLaunchKernelGGL(k_numeric_mpart<MODE_EXPAND>, dim3(pgrid), dim3(MPP_NW * WAVE), 0, st, a);
+            hipLaunchKernelGGL((k_finish_mpass<MODE_EXPAND, true>), dim3(grid), dim3(1024), 0, st, a,
+                               (char *)slab, slab_bytes);
+        } else {
+            hipLaunchKernelGGL(k_numeric_mpass<MODE_EXPAND>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
+            hipLaunchKernelGGL((k_finish_mpass<MODE_EXPAND, false>), dim3(grid), dim3(1024), 0, st, a,
+                               (char *)slab, slab_bytes);
+        }
     } else {
-        hipLaunchKernelGGL(k_numeric_mpass<MODE_ITERATE>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
-        hipLaunchKernelGGL(k_finish_mpass<MODE_ITERATE>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
-                           slab_bytes);
+        if (split) {
+            hipLaunchKernelGGL(k_numeric_mpart<MODE_ITERATE>, dim3(pgrid), dim3(MPP_NW * WAVE), 0, st, a);
+            hipLaunchKernelGGL((k_finish_mpass<MODE_ITERATE, true>), dim3(grid), dim3(1024), 0, st, a,
+                               (char *)slab, slab_bytes);
+        } else {
+            hipLaunchKernelGGL(k_numeric_mpass<MODE_ITERATE>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
+            hipLaunchKernelGGL((k_finish_mpass<MODE_ITERATE, false>), dim3(grid), dim3(1024), 0, st, a,
+                               (char *)slab, slab_bytes);
+        }
     }
 }
 
