@@ -205,42 +205,118 @@ def _line(metric, value, unit, ms, higher, workload, extra, steps=1, warmup=0, d
     return d
 
 
-def bench_merge(args):
-    """Section 4 / Alg. 2: the inner dimension of A*A (1M-vertex planted graph)
-    cut into 8 SUMMA stages; partial products merged by the binary schedule
-    vs all at once."""
+def bench_merge(args, sample_cols=4096, seed=11):
+    """One process's share of a 2D Sparse SUMMA product (Section 2 "Overview
+    of Sparse SUMMA", Section 4 and Alg. 2) at its real block shape: the
+    planted graph on 10,000,000 vertices (~480 nnz/column, seed 1002) on an
+    8 x 8 process grid, position (0, 1): 8 stage products A[0,k] * A[k,1] of
+    1.25M x 1.25M blocks (~60 nnz/column each), the partials merged by the
+    binary schedule (Alg. 2) or all at once, with the merges on the same stream
+    as the products or on a second stream overlapped with them."""
+    import numpy as np
     import torch
-    from mclgen import config1_graph
+    import oracle
+    from mclgen.planted import stripe_blocks
     from paper_2002_10083_amd import drivers, mcl, tuning
-    W = config1_graph(n=args.n, n_clusters=max(1, args.n // 20))
-    A = mcl.DeviceCSC.from_host(W)
-    mcl.normalize_(A)
+    t0 = time.time()
+    R, Cb = stripe_blocks(N=args.merge_n, grid=8, row_stripe=0, col_stripe=1, workers=16)
+    log("generated 16 blocks of %d x %d in %.1f s (nnz %s / %s)" % (R[0].nrows, R[0].ncols, time.time() - t0,
+                                                                   [x.nnz for x in R], [x.nnz for x in Cb]))
+    dR = [mcl.DeviceCSC.from_host(x) for x in R]
+    dC = [mcl.DeviceCSC.from_host(x) for x in Cb]
+    torch.cuda.synchronize()
     policy, scale, keys = tuning.load_policy("iterate")
     params = mcl.default_params(bin_policy=policy, est_scale=scale, cohen_keys=keys)
-    res = {}
-    for sched in ("binary", "flat", "binary"):       # first run warms up
+
+    def operands(i):
+        return dR[i], dC[i]
+
+    res, keep = {}, {}
+    # the first two runs warm up (kernels, and torch's cache grows to the
+    # larger peak once: fresh device memory is slow to map on first use, so
+    # the cache is kept between runs)
+    plan = [("flat", False), ("binary", False), ("binary", False), ("flat", False), ("binary", True),
+            ("flat", True)]
+    for n, (sched, ov) in enumerate(plan):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
         torch.cuda.reset_peak_memory_stats()
-        C, info = drivers.summa_merge(A, 8, sched, params)
-        info["torch_peak_bytes"] = torch.cuda.max_memory_allocated()
-        res[sched] = info
+        run = drivers.summa_stages_overlapped if ov else drivers.summa_stages
+        ms0 = torch.cuda.memory_stats()
+        C, info = run(operands, 8, sched, params)
+        ms1 = torch.cuda.memory_stats()
+        info["peak_device_bytes"] = int(torch.cuda.max_memory_allocated() - base)
+        info["alloc_retries"] = int(ms1.get("num_alloc_retries", 0) - ms0.get("num_alloc_retries", 0))
+        info["device_allocs"] = int(ms1.get("num_device_alloc", 0) - ms0.get("num_device_alloc", 0))
+        key = sched + ("_overlap" if ov else "")
+        res[key] = info
+        log("%s: expand %.1f ms, merge %.1f ms, wall %.1f ms, peak %.2f GB, nnz %d, alloc retries %d, "
+            "device allocs %d" % (key, info["t_expand_ms"], info["t_merge_ms"], info["wall_ms"],
+                                  info["peak_device_bytes"] / 1e9, info["nnz"], info["alloc_retries"],
+                                  info["device_allocs"]))
+        for c in info["merge_calls"]:
+            log("   merge of %d lists: in %d out %d, %.1f ms, bins ms %s cols %s" %
+                (c["lists"], c["in_nnz"], c["out_nnz"], c["ms"], [round(x, 1) for x in c["bin_ms"]],
+                 c["bin_cols"]))
+        if n > 1 and not ov:
+            # sampled output columns for the parity check against the oracle
+            rng = np.random.default_rng(seed)
+            cols = np.sort(rng.choice(C.ncols, size=min(sample_cols, C.ncols), replace=False))
+            keep[sched] = _download_columns(C, cols)
         del C
-        torch.cuda.empty_cache()
-    b, f = res["binary"], res["flat"]
-    tot_b = b["t_expand_ms"] + b["t_merge_ms"]
-    tot_f = f["t_expand_ms"] + f["t_merge_ms"]
-    merged_in = sum(b["partial_nnz"])
-    return _line("merge throughput of the binary (Alg. 2) schedule: partial-product nnz merged per s",
-                 round(merged_in / (b["t_merge_ms"] * 1e-3), 1), "nnz/s", tot_b, True,
-                 "8 SUMMA stages of A*A on the 1M-vertex planted graph (seed 1001); partials merged "
-                 "by Alg. 2 vs one 8-way merge",
-                 {"binary": {k: b[k] for k in ("t_expand_ms", "t_merge_ms", "peak_list_bytes",
-                                               "torch_peak_bytes", "merges", "nnz")},
-                  "flat": {k: f[k] for k in ("t_expand_ms", "t_merge_ms", "peak_list_bytes",
-                                             "torch_peak_bytes", "merges", "nnz")},
-                  "partial_nnz": b["partial_nnz"],
-                  "merge_share_binary": round(b["t_merge_ms"] / tot_b, 4),
-                  "time_binary_over_flat": round(tot_b / tot_f, 4),
-                  "peak_list_bytes_binary_over_flat": round(b["peak_list_bytes"] / f["peak_list_bytes"], 4)})
+    # parity on sampled columns: the oracle's stage products of those columns,
+    # merged by the oracle's heap merge with the same schedule
+    t1 = time.time()
+    cols = keep["binary"][0]
+    parts = [oracle.expand(R[k], Cb[k].restrict_columns(cols))[0] for k in range(8)]
+    ref_b, _ = oracle.binary_merge(parts)
+    ref_f = oracle.merge(parts)
+    par = {}
+    for sched, ref in (("binary", ref_b), ("flat", ref_f)):
+        _, cp, row, val = keep[sched]
+        same = np.array_equal(cp, ref.colptr) and np.array_equal(row, ref.rowidx) and np.array_equal(val, ref.val)
+        par[sched] = {"columns": int(len(cols)), "entries": int(ref.nnz), "bit_identical": bool(same)}
+    log("merge parity took %.1f s: %s" % (time.time() - t1, par))
+    b, bo, f = res["binary"], res["binary_overlap"], res["flat"]
+    merged_in = sum(c["in_nnz"] for c in b["merge_calls"])
+    mb = sum(c["bytes"] for c in b["merge_calls"])
+    mms = sum(c["ms"] for c in b["merge_calls"])
+    roof = {"bound": "hbm", "achieved": round(mb / (mms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(mb / (mms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "merge calls of the binary schedule (sequential run)", "ms": round(mms, 3),
+            "algorithmic_bytes": int(mb)}
+    pick = ("t_expand_ms", "t_merge_ms", "wall_ms", "peak_list_bytes", "peak_device_bytes", "merges", "nnz")
+    out = {k: {q: res[k][q] for q in pick} for k in res}
+    for k in ("binary_overlap", "flat_overlap"):
+        out[k]["overlap_frac"] = round(res[k]["overlap_frac"], 4)
+    return _line("SUMMA stage products + merge at the real block shape: partial-product nnz merged per s "
+                 "(binary schedule, overlapped)",
+                 round(merged_in / (bo["wall_ms"] * 1e-3), 1), "nnz/s", bo["wall_ms"], True,
+                 "one process's share of a 10M-vertex planted graph on an 8x8 grid (position (0,1), seed 1002): "
+                 "8 products of 1.25M x 1.25M blocks, partials merged by Alg. 2 vs one 8-way merge, "
+                 "on one stream or overlapped on two",
+                 {"runs": out, "partial_nnz": b["partial_nnz"],
+                  "expand_flops_note": "see stage sizes", "merge_roofline": roof,
+                  "merge_share_binary": round(b["t_merge_ms"] / b["wall_ms"], 4),
+                  "time_binary_over_flat": round(b["wall_ms"] / f["wall_ms"], 4),
+                  "peak_list_bytes_binary_over_flat": round(b["peak_list_bytes"] / f["peak_list_bytes"], 4),
+                  "wall_overlapped_over_sequential": round(bo["wall_ms"] / b["wall_ms"], 4),
+                  "parity": par})
+
+
+def _download_columns(C, cols):
+    """Host copies of the given columns of a device CSC: (cols, colptr, rows, values)."""
+    import numpy as np
+    import torch
+    ct = torch.from_numpy(cols.astype(np.int64)).to(C.colptr.device)
+    s = C.colptr[ct]
+    cnt = C.colptr[ct + 1] - s
+    total = int(cnt.sum())
+    start = torch.cumsum(cnt, 0) - cnt
+    idx = torch.repeat_interleave(s - start, cnt) + torch.arange(total, device=s.device)
+    cp = np.zeros(len(cols) + 1, np.int64)
+    cp[1:] = np.cumsum(cnt.cpu().numpy())
+    return cols, cp, C.rowidx[idx].cpu().numpy(), C.val[idx].cpu().numpy()
 
 
 def bench_batched(args, sample=300, seed=5):
@@ -361,6 +437,8 @@ def main():
                     help="bin launch policy (default: tuned table if present)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--merge-n", type=int, default=10_000_000,
+                    help="merge workload: vertices of the whole graph (8 x 8 grid)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--workload", default="iterate", choices=["iterate", "merge", "batched", "mlp"],

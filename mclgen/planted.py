@@ -509,7 +509,7 @@ def two_triangles() -> CSC:
 # --------------------------------------------------------------------------
 
 def stripe_blocks(N=10_000_000, grid=8, row_stripe=0, col_stripe=1, target_nnz_per_col=480.0,
-                  alpha=2.0, s_min=3, p_in=0.3, x=0.05, seed=1002, scale=None):
+                  alpha=2.0, s_min=3, p_in=0.3, x=0.05, seed=1002, scale=None, workers=8):
     """Blocks A[row_stripe, k] and A[k, col_stripe] (k = 0..grid-1) of one
     planted graph on N vertices, generated block by block without building the
     rest of the graph.
@@ -519,7 +519,9 @@ def stripe_blocks(N=10_000_000, grid=8, row_stripe=0, col_stripe=1, target_nnz_p
     symmetric graph.  Global column sums are not available to a single block
     row/column, so every weight is multiplied by ``scale`` (default
     1/target_nnz_per_col, the magnitude of a column-normalised entry); diagonal
-    blocks get unit self-loops.  Returns (A_row: list of CSC, A_col: list of CSC).
+    blocks get unit self-loops.  Blocks are generated by `workers` threads
+    (the result does not depend on it).  Returns (A_row: list of CSC, A_col:
+    list of CSC).
     """
     base = np.random.Generator(np.random.PCG64(seed))
     n_clusters = max(1, int(round(N / 21.6)))
@@ -552,9 +554,8 @@ def stripe_blocks(N=10_000_000, grid=8, row_stripe=0, col_stripe=1, target_nnz_p
 
     cache = {}
 
-    def block(I, K):
-        key = (min(I, K), max(I, K))
-        if key not in cache:
+    def gen_block(key):
+        if True:
             a_, b_ = key
             rng = np.random.Generator(np.random.PCG64([seed, a_, b_]))
             selA, cntA, ptrA = members(a_)
@@ -600,7 +601,19 @@ def stripe_blocks(N=10_000_000, grid=8, row_stripe=0, col_stripe=1, target_nnz_p
             m = sp.csc_matrix((ww, (rr, cc)), shape=(bs, bs))
             m.sum_duplicates()
             m.sort_indices()
-            cache[key] = m
+            return m
+
+    # every block pair once (each from its own RNG stream), several at a time
+    keys = sorted({(min(row_stripe, k), max(row_stripe, k)) for k in range(grid)}
+                  | {(min(k, col_stripe), max(k, col_stripe)) for k in range(grid)})
+    for I in sorted({i for kk in keys for i in kk}):
+        members(I)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(workers, len(keys)))) as ex:
+        cache = dict(zip(keys, ex.map(gen_block, keys)))
+
+    def block(I, K):
+        key = (min(I, K), max(I, K))
         m = cache[key]
         if (I, K) != (min(I, K), max(I, K)):
             m = m.T.tocsc()

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcl.so")
-SOURCES = ["api.hip", "spgemm.hip", "prune.hip", "mlp.hip", "components.hip"]
+SOURCES = ["api.hip", "spgemm.hip", "prune.hip", "mlp.hip", "components.hip", "merge.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -1037,6 +1037,8 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
     return with_mem(alloc, stream, C, [&](Mem &mem) {
         if (!C) fail(MCL_EINVAL, "C is NULL");
         if (!parts || nparts <= 0) fail(MCL_EINVAL, "need at least one part");
+        if (nparts > mcl::merge_max_parts())
+            fail(MCL_EINVAL, "at most " + std::to_string(mcl::merge_max_parts()) + " parts per merge");
         for (int l = 0; l < nparts; ++l) {
             check_csc(&parts[l], "part");
             if (parts[l].nrows != parts[0].nrows || parts[l].ncols != parts[0].ncols)
@@ -1049,47 +1051,48 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
         for (int l = 0; l < nparts; ++l) h[l] = dev(parts[l]);
         mcl::DevCSC *dparts = mem.ws<mcl::DevCSC>(nparts);
         HIPC(hipMemcpyAsync(dparts, h.data(), nparts * sizeof(mcl::DevCSC), hipMemcpyHostToDevice, mem.st));
-        HIPC(hipStreamSynchronize(mem.st));
-        ProductPlan pl;
-        pl.flops = mem.ws<int64_t>(n);
-        pl.lo = mem.ws<int32_t>(n);
-        pl.hi = mem.ws<int32_t>(n);
-        pl.bin = mem.ws<int32_t>(n);
-        pl.capv = mem.ws<int64_t>(n + 1);
-        pl.base = mem.ws<int64_t>(n + 1);
-        pl.cnt = mem.ws<int64_t>(n);
-        pl.lists = mem.ws<int32_t>(n);
-        pl.hbm_only = mem.ws<uint8_t>(n);
-        HIPC(hipMemsetAsync(pl.hbm_only, 0, n, mem.st));
-        mcl::launch_merge_plan(dparts, nparts, n, pl.flops, pl.lo, pl.hi, mem.st);
-        int32_t *bc = mem.ws<int32_t>(8);
-        int64_t *mg = mem.ws<int64_t>(1);
-        HIPC(hipMemsetAsync(bc, 0, 8 * sizeof(int32_t), mem.st));
-        HIPC(hipMemsetAsync(mg, 0, sizeof(int64_t), mem.st));
-        mcl::launch_plan(n, pl.flops, pl.lo, pl.hi, nullptr, MCL_EST_BOUND, 1.0, nrows, nullptr, pl.bin,
-                         pl.capv, bc, mg, mem.st);
-        int64_t *tmp = mem.ws<int64_t>(mcl::exscan_tmp_elems(n));
-        mcl::launch_exscan_i64(pl.capv, pl.base, n, tmp, mem.st);
-        HIPC(hipMemcpyAsync(pl.counts, bc, sizeof(pl.counts), hipMemcpyDeviceToHost, mem.st));
-        HIPC(hipMemcpyAsync(&pl.max_global, mg, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
-        HIPC(hipMemcpyAsync(&pl.temp_total, pl.base + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
-        HIPC(hipStreamSynchronize(mem.st));
-        mcl::NumericArgs a{};
-        a.parts = dparts;
-        a.nparts = nparts;
-        a.A.nrows = nrows;
-        EngineOut eo;
         if (stats) std::memset(stats, 0, sizeof(*stats));
-        engine(mem, n, nrows, mcl::MODE_EXPAND, a, pl, eo, tm);
         int64_t *colptr = mem.out<int64_t>(n + 1);
-        const int64_t nnz = scan_counts(mem, pl.cnt, n, colptr);
-        int32_t *row = mem.out<int32_t>(nnz);
-        double *val = mem.out<double>(nnz);
-        mcl::launch_compact(n, nullptr, pl.base, pl.cnt, colptr, eo.tr, row, val, mem.st);
+        int64_t nnz = 0, ntiles = 0;
+        int32_t *row = nullptr;
+        double *val = nullptr;
+        if (n == 0) {
+            HIPC(hipMemsetAsync(colptr, 0, sizeof(int64_t), mem.st));
+        } else {
+            // tiles per column, their columns and first rows
+            int64_t *ntile = mem.ws<int64_t>(n);
+            int64_t *tile_ptr = mem.ws<int64_t>(n + 1);
+            mcl::launch_merge_ntiles(dparts, nparts, n, ntile, mem.st);
+            int64_t *tmp = mem.ws<int64_t>(mcl::exscan_tmp_elems(n));
+            mcl::launch_exscan_i64(ntile, tile_ptr, n, tmp, mem.st);
+            HIPC(hipMemcpyAsync(&ntiles, tile_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipStreamSynchronize(mem.st));
+            int32_t *tile_col = mem.ws<int32_t>(ntiles);
+            int32_t *tile_row = mem.ws<int32_t>(ntiles);
+            int64_t *tile_cnt = mem.ws<int64_t>(ntiles);
+            int64_t *tile_off = mem.ws<int64_t>(ntiles + 1);
+            int32_t *err = mem.ws<int32_t>(1);
+            HIPC(hipMemsetAsync(err, 0, sizeof(int32_t), mem.st));
+            mcl::launch_merge_bounds(dparts, nparts, nrows, n, tile_ptr, tile_col, tile_row, mem.st);
+            // count pass, output offsets, fill pass
+            mcl::launch_merge_tiles(false, dparts, nparts, nrows, ntiles, tile_ptr, tile_col, tile_row, tile_cnt,
+                                    nullptr, nullptr, nullptr, err, mem.st);
+            int64_t *tmp2 = mem.ws<int64_t>(mcl::exscan_tmp_elems(ntiles));
+            mcl::launch_exscan_i64(tile_cnt, tile_off, ntiles, tmp2, mem.st);
+            int32_t herr = 0;
+            HIPC(hipMemcpyAsync(&nnz, tile_off + ntiles, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
+            HIPC(hipStreamSynchronize(mem.st));
+            if (herr) fail(MCL_EINVAL, "part: rows are not strictly ascending within a column");
+            row = mem.out<int32_t>(nnz);
+            val = mem.out<double>(nnz);
+            mcl::launch_merge_colptr(n, tile_ptr, tile_off, colptr, mem.st);
+            mcl::launch_merge_tiles(true, dparts, nparts, nrows, ntiles, tile_ptr, tile_col, tile_row, nullptr,
+                                    tile_off, row, val, err, mem.st);
+        }
         HIPC(hipGetLastError());
         tm.mark();
         HIPC(hipStreamSynchronize(mem.st));
-        copy_bin_stats(eo, stats);
         C->nrows = nrows;
         C->ncols = n;
         C->nnz = nnz;
@@ -1099,11 +1102,10 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
         if (stats) {
             stats->nnz_product = nnz;
             stats->nnz_kept = nnz;
-            stats->n_overflow = eo.n_overflow;
-            stats->n_global = eo.n_global;
             stats->t_merge_ms = tm.ms(0, tm.ev.size() - 1);
             stats->t_total_ms = stats->t_merge_ms;
             stats->peak_workspace_bytes = (int64_t)mem.peak;
+            stats->bin_cols[7] = ntiles;  // merge tiles
         }
     });
 }

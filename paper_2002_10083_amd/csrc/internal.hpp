@@ -151,6 +151,20 @@ void launch_normalize(int64_t ncols, const int64_t *colptr, double *val, hipStre
 void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
                        int32_t *hi, hipStream_t st);
 
+// ---- merge.hip: sorted multiway merge of same-shape partial products
+constexpr int MT_MAX_PARTS = 256;                      // lists one merge call accepts
+int merge_max_parts();
+int64_t merge_tile_elems(int nparts);                  // target elements per tile
+void launch_merge_ntiles(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ntile, hipStream_t st);
+void launch_merge_bounds(const DevCSC *parts, int nparts, int64_t nrows, int64_t ncols, const int64_t *tile_ptr,
+                         int32_t *tile_col, int32_t *tile_row, hipStream_t st);
+void launch_merge_tiles(bool fill, const DevCSC *parts, int nparts, int64_t nrows, int64_t ntiles,
+                        const int64_t *tile_ptr, const int32_t *tile_col, const int32_t *tile_row,
+                        int64_t *tile_cnt, const int64_t *tile_off, int32_t *out_row, double *out_val,
+                        int32_t *err, hipStream_t st);
+void launch_merge_colptr(int64_t ncols, const int64_t *tile_ptr, const int64_t *tile_off, int64_t *colptr,
+                         hipStream_t st);
+
 // ---- components.hip
 // weakly connected components of the pattern of a square A; label = smallest vertex id.
 // parent: int32[nrows] scratch; nroots: one int64, cleared by the first kernel.

@@ -1,7 +1,8 @@
 """Host-side drivers over the C-ABI calls (argument handling and loop control
 only; every arithmetic step runs in the library's kernels).
 
-* ``summa_merge``: the inner dimension of C = A*A is cut into ``nstages``
+* ``summa_merge`` / ``summa_stages`` / ``summa_stages_overlapped``: the
+  inner dimension of C = A*A (or given stage operand pairs) is cut into ``nstages``
   contiguous ranges K_1..K_s, stage i contributes the partial product
   A[:, K_i] * A[K_i, :] (one SUMMA stage of one process, Section 4), and the
   partials are merged either with the binary schedule of Alg. 2 (after stage
@@ -61,11 +62,28 @@ def binary_schedule(nstages: int) -> List[int]:
     return out
 
 
-def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", params=None):
+def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", params=None,
+                overlap: bool = False):
     """C = sum over stages of A[:, K_i] A[K_i, :], merged per `schedule`
     ("binary" = Alg. 2, "flat" = one merge of all partials at the end).
     Returns (C, info) with expansion and merge times (ms), the peak bytes held
     by partial and merged lists, and the per-stage list sizes."""
+    ranges = stage_ranges(A.ncols, nstages)
+
+    def operands(i):
+        k0, k1 = ranges[i]
+        return column_block(A, k0, k1), row_block(A, k0, k1)
+
+    if overlap:
+        return summa_stages_overlapped(operands, nstages, schedule, params)
+    return summa_stages(operands, nstages, schedule, params)
+
+
+def summa_stages(operands, nstages: int, schedule: str = "binary", params=None):
+    """One process's Sparse SUMMA stages on one stream: stage i multiplies the
+    pair operands(i) = (A_i, B_i) (same output shape for every stage) and the
+    partial products are merged per `schedule` (see summa_merge).  Returns
+    (C, info) as summa_merge."""
     if schedule not in ("binary", "flat"):
         raise ValueError(schedule)
     stack: List[mcl.DeviceCSC] = []
@@ -74,22 +92,25 @@ def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", 
     sizes = []
     merges = []
 
+    calls = []
+
     def merge(lists):
         nonlocal live, peak, t_mrg
         torch.cuda.synchronize()
         t = time.perf_counter()
-        M, _ = mcl.merge_partials(lists)
+        M, st = mcl.merge_partials(lists)
         torch.cuda.synchronize()
         t_mrg += (time.perf_counter() - t) * 1e3
         peak = max(peak, live + csc_bytes(M))
         live += csc_bytes(M) - sum(csc_bytes(x) for x in lists)
         merges.append(len(lists))
+        calls.append(merge_call_info(lists, M, st))
         return M
 
     plan = binary_schedule(nstages)
-    for i, (k0, k1) in enumerate(stage_ranges(A.ncols, nstages), start=1):
-        Ak = column_block(A, k0, k1)
-        Bk = row_block(A, k0, k1)
+    t_wall = time.perf_counter()
+    for i in range(1, nstages + 1):
+        Ak, Bk = operands(i - 1)
         torch.cuda.synchronize()
         t = time.perf_counter()
         P, _ = mcl.expand(Ak, Bk, params)
@@ -109,8 +130,108 @@ def summa_merge(A: "mcl.DeviceCSC", nstages: int = 8, schedule: str = "binary", 
         M = merge(stack)
         stack = [M]
     C = stack[0]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_wall) * 1e3
     return C, dict(t_expand_ms=t_exp, t_merge_ms=t_mrg, peak_list_bytes=peak, partial_nnz=sizes,
-                   merges=merges, nnz=C.nnz)
+                   merges=merges, nnz=C.nnz, wall_ms=wall, overlap=False, merge_calls=calls)
+
+
+def merge_call_info(lists, M, st):
+    """One merge call: list sizes, output size, the library's event time and
+    its algorithmic bytes (every input entry read once, 12 B, plus its colptr
+    pair, 16 B per column and list; every output entry written once, 12 B,
+    plus 8 B per column)."""
+    nin = sum(x.nnz for x in lists)
+    byt = 12 * nin + 16 * M.ncols * len(lists) + 12 * M.nnz + 8 * (M.ncols + 1)
+    return dict(lists=len(lists), in_nnz=nin, out_nnz=M.nnz, ms=st["t_merge_ms"], bytes=byt,
+                bin_ms=st["bin_ms"], bin_cols=st["bin_cols"])
+
+
+def summa_stages_overlapped(operands, nstages: int, schedule: str = "binary", params=None):
+    """summa_stages with the merges on a second stream, run by a host thread
+    of their own: the merge Alg. 2 schedules after stage i runs while stage
+    i+1 is multiplied on the caller's stream (the paper's pipelining of the
+    merge against the local multiplications, Section 3 and Section 4).  A
+    merge waits for the event recorded after the stage that produced its last
+    list; merges run in schedule order, so the lists an earlier merge produced
+    are complete.  Returns (C, info) as summa_merge, plus the busy time of
+    each stream, the wall time and the fraction of the merge time hidden
+    behind the products (overlap_frac = (t_expand + t_merge - wall) /
+    t_merge)."""
+    import threading
+    from concurrent.futures import Future, ThreadPoolExecutor
+
+    if schedule not in ("binary", "flat"):
+        raise ValueError(schedule)
+    dev = torch.cuda.current_device()
+    s_merge = torch.cuda.Stream(device=dev)      # default priority
+    lock = threading.Lock()
+    acct = dict(t_mrg=0.0, live=0, peak=0)
+    calls = []
+    merges: List[int] = []
+    sizes: List[int] = []
+
+    def add_live(delta):
+        with lock:
+            acct["live"] += delta
+            acct["peak"] = max(acct["peak"], acct["live"])
+
+    def run_merge(inputs, ready):
+        torch.cuda.set_device(dev)
+        lists = [x.result() if isinstance(x, Future) else x for x in inputs]
+        with torch.cuda.stream(s_merge):
+            s_merge.wait_event(ready)
+            t = time.perf_counter()
+            M, st = mcl.merge_partials(lists)
+            s_merge.synchronize()
+            dt = (time.perf_counter() - t) * 1e3
+        with lock:
+            acct["t_mrg"] += dt
+            calls.append(merge_call_info(lists, M, st))
+        add_live(csc_bytes(M))
+        add_live(-sum(csc_bytes(x) for x in lists))
+        del lists, inputs
+        return M
+
+    plan = binary_schedule(nstages)
+    stack = []
+    t_exp = 0.0
+    s_main = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=1) as ex:
+        for i in range(1, nstages + 1):
+            Ak, Bk = operands(i - 1)
+            t = time.perf_counter()
+            P, _ = mcl.expand(Ak, Bk, params)
+            s_main.synchronize()
+            t_exp += (time.perf_counter() - t) * 1e3
+            del Ak, Bk
+            ev = torch.cuda.Event()
+            ev.record(s_main)
+            sizes.append(P.nnz)
+            add_live(csc_bytes(P))
+            stack.append(P)
+            del P
+            if schedule == "binary" and plan[i - 1] > 0:
+                take = stack[-plan[i - 1]:]
+                del stack[-plan[i - 1]:]
+                stack.append(ex.submit(run_merge, take, ev))
+                merges.append(len(take))
+                del take
+        if len(stack) > 1:
+            ev = torch.cuda.Event()
+            ev.record(s_main)
+            merges.append(len(stack))
+            stack = [ex.submit(run_merge, list(stack), ev)]
+        C = stack[0].result() if isinstance(stack[0], Future) else stack[0]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_wall) * 1e3
+    t_mrg = acct["t_mrg"]
+    frac = (t_exp + t_mrg - wall) / t_mrg if t_mrg > 0 else 0.0
+    return C, dict(t_expand_ms=t_exp, t_merge_ms=t_mrg, peak_list_bytes=acct["peak"], partial_nnz=sizes,
+                   merges=merges, nnz=C.nnz, wall_ms=wall, overlap=True, overlap_frac=frac,
+                   merge_calls=calls)
 
 
 def batched_mcl(A: "mcl.DeviceCSC", comp_ptr: torch.Tensor, params=None, tol: float = 1e-9,

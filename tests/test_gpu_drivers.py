@@ -101,3 +101,40 @@ def test_summa_merge_large_columns(drv):
     assert np.array_equal(g.colptr, ref.colptr)
     assert np.array_equal(g.rowidx, ref.rowidx)
     assert np.array_equal(g.val, ref.val)
+
+
+_STRIPES = {}
+
+
+def _stripe_case():
+    """Stripe blocks of a 480,000-vertex planted graph (8 x 8 grid, position
+    (0, 1)) and the oracle's 8 stage products (computed once)."""
+    if not _STRIPES:
+        from mclgen.planted import stripe_blocks
+        R, Cb = stripe_blocks(N=480_000, grid=8, row_stripe=0, col_stripe=1, workers=4)
+        _STRIPES["case"] = (R, Cb, [oracle.expand(R[k], Cb[k])[0] for k in range(8)])
+    return _STRIPES["case"]
+
+
+@pytest.mark.parametrize("schedule", ["binary", "flat"])
+def test_stripe_blocks_overlapped_merge_matches_oracle(drv, schedule):
+    """One process's SUMMA share of a 2D-distributed planted graph (8 x 8
+    grid, position (0, 1), scaled down to 480,000 vertices): the overlapped
+    driver (merges on a second stream) equals the one-stream driver bit for
+    bit, and both equal the oracle's stage products merged by its heap merge
+    with the same schedule."""
+    drivers, mcl = drv
+    R, Cb, parts = _stripe_case()
+    dR = [mcl.DeviceCSC.from_host(x) for x in R]
+    dC = [mcl.DeviceCSC.from_host(x) for x in Cb]
+    ops = lambda i: (dR[i], dC[i])
+    C1, i1 = drivers.summa_stages(ops, 8, schedule)
+    C2, i2 = drivers.summa_stages_overlapped(ops, 8, schedule)
+    assert i2["merges"] == i1["merges"] == ([2, 3, 2, 4] if schedule == "binary" else [8])
+    assert torch.equal(C1.colptr, C2.colptr) and torch.equal(C1.rowidx, C2.rowidx)
+    assert torch.equal(C1.val, C2.val)
+    assert i2["peak_list_bytes"] >= max(drivers.csc_bytes(C1), 1)
+    ref = oracle.binary_merge(parts)[0] if schedule == "binary" else oracle.merge(parts)
+    g = C2.to_host()
+    assert np.array_equal(g.colptr, ref.colptr) and np.array_equal(g.rowidx, ref.rowidx)
+    assert np.array_equal(g.val, ref.val)
