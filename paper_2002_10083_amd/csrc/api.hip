@@ -282,7 +282,7 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
                 HIPC(hipEventCreate(&e0));
                 HIPC(hipEventCreate(&e1));
                 if (b < mcl::NUM_LDS_BINS && mcl::lds_variant_split(b, variant) && a.part_cnt &&
-                    mode != mcl::MODE_COUNT && !a.parts)
+                    mode != mcl::MODE_COUNT)
                     HIPC(hipEventCreate(&em));
                 HIPC(hipEventRecord(e0, mem.st));
             }
@@ -291,7 +291,7 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
             } else {
                 // multi-pass LDS kernel for the columns within its capacity,
                 // HBM-resident tables for the rest
-                if (mode != mcl::MODE_COUNT && a.goff && !a.parts) {
+                if (mode != mcl::MODE_COUNT && a.goff) {
                     const size_t mslab = mcl::mpass_slab_bytes();
                     const int mslabs = std::min<int>(c, 512);
                     char *ms = mem.ws<char>((int64_t)(mslab * mslabs));
@@ -474,7 +474,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         int32_t *nexact_d = dev_i + 9;
         int32_t *exact = mem.ws<int32_t>(novf);
         mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d,
-                         mode != mcl::MODE_COUNT && a.goff && !a.parts, round >= 2, mem.st);
+                         mode != mcl::MODE_COUNT && a.goff, round >= 2, mem.st);
         int32_t hc[9];
         HIPC(hipMemcpyAsync(hc, counts_d, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
         HIPC(hipStreamSynchronize(mem.st));

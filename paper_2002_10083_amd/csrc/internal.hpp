@@ -1,5 +1,6 @@
 // Host-side interface between the C-ABI layer (api.hip) and the kernel
-// launchers (spgemm.hip, prune.hip, merge.hip, mlp.hip).  Not installed.
+// launchers (spgemm.hip, prune.hip, merge.hip, mlp.hip, components.hip).
+// Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,8 +40,6 @@ struct NumericArgs {
     double *delta;            // per-column max change (ITERATE)
     int8_t *mode;             // per-column prune branch 0/1/2 (ITERATE)
     PruneArgs pa;
-    const DevCSC *parts;      // merge mode: device array of nparts matrices (else null)
-    int32_t nparts;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
     const int32_t *srow;     // sliced copy of A (column ranges of A.colptr): rows
@@ -148,8 +147,6 @@ void launch_inflate(int64_t ncols, const int64_t *colptr, double *val, double r,
                     hipStream_t st);
 void launch_normalize(int64_t ncols, const int64_t *colptr, double *val, hipStream_t st);
 
-void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
-                       int32_t *hi, hipStream_t st);
 
 // ---- merge.hip: sorted multiway merge of same-shape partial products
 constexpr int MT_MAX_PARTS = 256;                      // lists one merge call accepts

@@ -203,38 +203,6 @@ void launch_symbolic(const DevCSC &A, const DevCSC &B, int64_t *flops, int32_t *
 #undef MCL_SYM
 }
 
-// Merge planning: for column j, ub_j = sum over parts of nnz (the exact-safe
-// bound on the merged column) and the row span over all parts.
-__global__ __launch_bounds__(256) void k_merge_plan(const DevCSC *__restrict__ parts, int nparts,
-                                                    int64_t ncols, int64_t *__restrict__ ub,
-                                                    int32_t *__restrict__ lo, int32_t *__restrict__ hi)
-{
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ncols;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        int64_t n = 0;
-        int mn = INT32_MAX, mx = -1;
-        for (int l = 0; l < nparts; ++l) {
-            const DevCSC &P = parts[l];
-            const int64_t s = P.colptr[j], e = P.colptr[j + 1];
-            n += e - s;
-            if (e > s) {
-                mn = min(mn, P.rowidx[s]);
-                mx = max(mx, P.rowidx[e - 1]);
-            }
-        }
-        ub[j] = n;
-        lo[j] = (mx >= 0) ? mn : 0;
-        hi[j] = (mx >= 0) ? mx : 0;
-    }
-}
-
-void launch_merge_plan(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ub, int32_t *lo,
-                       int32_t *hi, hipStream_t st)
-{
-    if (ncols == 0) return;
-    const unsigned grid = (unsigned)std::min<int64_t>((ncols + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_merge_plan, dim3(grid), dim3(256), 0, st, parts, nparts, ncols, ub, lo, hi);
-}
 
 // ---------------------------------------------------------------------------
 // Cohen's estimator (Section 5): exponential keys on the first layer (rows of
@@ -1161,7 +1129,7 @@ __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t
 }
 
 // The numeric body for one column j, executed by NT threads.
-template <int NT, int MODE, int E, int D, typename IdxT, bool IS_MERGE, bool GS, bool PIPE = false>
+template <int NT, int MODE, int E, int D, typename IdxT, bool GS, bool PIPE = false>
 __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, int cap, int NB,
                            const Scratch<IdxT> &sc)
 {
@@ -1178,12 +1146,10 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
     group_sync<NT, GS>();
 
     // ---------------- accumulation ----------------
-    // Step t of column j adds b_t * (column t of the source) to the table:
-    // SpGEMM: source column = A_*k for the t-th nonzero b_kj of B_*j;
-    // merge:  source column = column j of part t, with b_t = 1 (v * 1 is
-    //         exact, so parts are summed in order).
-    const int64_t bs = IS_MERGE ? 0 : a.B.colptr[j];
-    const int mj = IS_MERGE ? a.nparts : (int)(a.B.colptr[j + 1] - bs);
+    // Step t of column j adds b_t * A_*k to the table, for the t-th nonzero
+    // b_kj of B_*j.
+    const int64_t bs = a.B.colptr[j];
+    const int mj = (int)(a.B.colptr[j + 1] - bs);
     // Key count and overflow: each wave counts the keys it placed.  At the
     // end of every burst group the waves publish their counts and read all
     // of them back; the slots alternate between two sets by group parity,
@@ -1203,20 +1169,12 @@ __device__ void column_body(const NumericArgs &a, int64_t j, int S, int logS, in
         int klen = 0;
         double bv = 1.0;
         if (t < mj) {
-            if constexpr (IS_MERGE) {
-                const DevCSC &P = a.parts[t];
-                const int64_t p0 = P.colptr[j];
-                rp = P.rowidx + p0;
-                vp = P.val + p0;
-                klen = (int)(P.colptr[j + 1] - p0);
-            } else {
-                const int k = a.B.rowidx[bs + t];
-                bv = a.B.val[bs + t];
-                const int64_t p0 = a.A.colptr[k];
-                rp = a.A.rowidx + p0;
-                vp = a.A.val + p0;
-                klen = (int)(a.A.colptr[k + 1] - p0);
-            }
+            const int k = a.B.rowidx[bs + t];
+            bv = a.B.val[bs + t];
+            const int64_t p0 = a.A.colptr[k];
+            rp = a.A.rowidx + p0;
+            vp = a.A.val + p0;
+            klen = (int)(a.A.colptr[k + 1] - p0);
         }
         const int nb = min(WAVE, mj - tb);
         // Every step of the batch is cut into ceil(len/CH) chunks (at least
@@ -1384,7 +1342,7 @@ struct LdsBin {
     using Idx = uint16_t;
 };
 
-template <int S, int NW, int CPW, int MODE, int E, int D, bool IS_MERGE, bool PIPE>
+template <int S, int NW, int CPW, int MODE, int E, int D, bool PIPE>
 __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
 {
     using L = LdsBin<S>;
@@ -1409,7 +1367,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
     Scratch<uint16_t> sc{c.key, c.val, c.list, c.sorted, c.bcnt, c.bcur, c.p0, c.p1,
                          c.ip, c.hist, c.misc, c.dmisc, c.wsum};
     constexpr int logS = __builtin_ctz(S);
-    column_body<NT, MODE, E, D, uint16_t, IS_MERGE, false, PIPE>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
+    column_body<NT, MODE, E, D, uint16_t, false, PIPE>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -2114,7 +2072,7 @@ size_t mpass_slab_bytes()
 void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
                           hipStream_t st)
 {
-    if (a.ncols <= 0 || !a.goff || a.parts || mode == MODE_COUNT) return;
+    if (a.ncols <= 0 || !a.goff || mode == MODE_COUNT) return;
     const int grid = std::min(nslabs, a.ncols);
     const unsigned pgrid = (unsigned)(((a.ncols + 7) / 8) * 8 * MPP_P);
     const bool split = a.part_cnt != nullptr;
@@ -2146,22 +2104,22 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
 // the sliced-table kernel (waves, chunks per group; reads the sliced source
 // layout).  Variant 0 is the fastest shape measured on the 1M-vertex planted
 // graph; the others are alternatives the tuner may select through
-// mcl_params.bin_policy (4 bits per bin).  Merge and exact-count launches use
-// the shared-table shape (shared_table_variant).
-template <int MODE, bool IS_MERGE>
+// mcl_params.bin_policy (4 bits per bin).  Exact-count launches use the
+// shared-table shape (shared_table_variant).
+template <int MODE>
 static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStream_t st, hipEvent_t mid = nullptr)
 {
     const int n = a.ncols;
     if (n <= 0) return;
 #define MCL_LAUNCH(S_, NW_, CPW_, E_, D_, P_)                                               \
-    hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, IS_MERGE, P_>),          \
+    hipLaunchKernelGGL((k_numeric_lds<S_, NW_, CPW_, MODE, E_, D_, P_>),                    \
                        dim3((n + CPW_ - 1) / CPW_), dim3(NW_ * WAVE * CPW_), 0, st, a)
 #define MCL_SPLIT_W(NW_, SW_, D_)                                                            \
-    if constexpr (!IS_MERGE && MODE != MODE_COUNT)                                           \
+    if constexpr (MODE != MODE_COUNT)                                                        \
         hipLaunchKernelGGL((k_numeric_hsplit<NW_, SW_, MODE, D_>), dim3(n), dim3(NW_ * WAVE), 0, st, a)
 #define MCL_SPLIT(NW_, D_) MCL_SPLIT_W(NW_, 512, D_)
 #define MCL_PART(NWP_, SW_, P_, D_, CAPF_, WPE_)                                             \
-    if constexpr (!IS_MERGE && MODE != MODE_COUNT) launch_part<NWP_, SW_, P_, MODE, D_, CAPF_, WPE_>(a, st, mid)
+    if constexpr (MODE != MODE_COUNT) launch_part<NWP_, SW_, P_, MODE, D_, CAPF_, WPE_>(a, st, mid)
     switch (bin * 8 + variant) {
     case 0: MCL_LAUNCH(128, 1, 4, 2, 4, false); break;
     case 1: MCL_LAUNCH(128, 1, 4, 1, 8, false); break;
@@ -2205,7 +2163,7 @@ static void launch_lds_mode(int bin, int variant, const NumericArgs &a, hipStrea
     case 60: MCL_PART(4, 512, 4, 2, 6144, 1); break;
     case 61: MCL_PART(1, 512, 16, 2, 6144, 8); break;
     case 62: MCL_PART(4, 512, 4, 1, 6144, 8); break;
-    default: launch_lds_mode<MODE, IS_MERGE>(bin, 0, a, st); break;
+    default: launch_lds_mode<MODE>(bin, 0, a, st); break;
     }
 #undef MCL_PART
 #undef MCL_SPLIT
@@ -2225,8 +2183,8 @@ bool lds_variant_split(int bin, int variant)
            (bin == 6 && variant >= 6);
 }
 
-// Launch used by merges and exact counts (modes the sliced kernels do not
-// serve): the shared-table shape of the bin.
+// Launch used by exact counts (a mode the sliced kernels do not serve): the
+// shared-table shape of the bin.
 static int shared_table_variant(int bin) { return (bin >= 3 && bin <= 6) ? 1 : 0; }
 
 int lds_bin_variants(int bin)
@@ -2238,16 +2196,12 @@ int lds_bin_variants(int bin)
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,
                         hipEvent_t mid)
 {
-    if (a.parts) {
-        launch_lds_mode<MODE_EXPAND, true>(bin, shared_table_variant(bin), a, st);
-        return;
-    }
     if (lds_variant_split(bin, variant) && !a.part_cnt) variant = 0;
     if (lds_variant_sliced(bin, variant) && !a.goff) variant = shared_table_variant(bin);
     switch (mode) {
-    case MODE_COUNT: launch_lds_mode<MODE_COUNT, false>(bin, shared_table_variant(bin), a, st); break;
-    case MODE_EXPAND: launch_lds_mode<MODE_EXPAND, false>(bin, variant, a, st, mid); break;
-    case MODE_ITERATE: launch_lds_mode<MODE_ITERATE, false>(bin, variant, a, st, mid); break;
+    case MODE_COUNT: launch_lds_mode<MODE_COUNT>(bin, shared_table_variant(bin), a, st); break;
+    case MODE_EXPAND: launch_lds_mode<MODE_EXPAND>(bin, variant, a, st, mid); break;
+    case MODE_ITERATE: launch_lds_mode<MODE_ITERATE>(bin, variant, a, st, mid); break;
     }
 }
 
@@ -2281,7 +2235,7 @@ static __host__ __device__ SlabLayout slab_layout(int S, int cap)
 }
 size_t global_slab_bytes(int S, int cap) { return slab_layout(S, cap).bytes; }
 
-template <int MODE, bool IS_MERGE>
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_numeric_global(NumericArgs a, int S, int cap, char *slab,
                                                          size_t slab_bytes)
 {
@@ -2301,8 +2255,8 @@ __global__ __launch_bounds__(1024) void k_numeric_global(NumericArgs a, int S, i
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
         const int64_t j = a.cols[idx];
         // columns of the multi-pass LDS kernel are done there (not in count mode)
-        if (!IS_MERGE && MODE != MODE_COUNT && multipass_column(a, j)) continue;
-        column_body<NT, MODE, 1, 2, int32_t, IS_MERGE, true>(a, j, S, logS, cap, NB, sc);
+        if (MODE != MODE_COUNT && multipass_column(a, j)) continue;
+        column_body<NT, MODE, 1, 2, int32_t, true>(a, j, S, logS, cap, NB, sc);
         __syncthreads();
     }
 }
@@ -2312,22 +2266,17 @@ void launch_numeric_global(NumericMode mode, const NumericArgs &a, int S, int ca
 {
     if (a.ncols <= 0) return;
     const int grid = std::min(nslabs, a.ncols);
-    if (a.parts) {
-        hipLaunchKernelGGL((k_numeric_global<MODE_EXPAND, true>), dim3(grid), dim3(1024), 0, st, a, S,
-                           cap, (char *)slab, slab_bytes);
-        return;
-    }
     switch (mode) {
     case MODE_COUNT:
-        hipLaunchKernelGGL((k_numeric_global<MODE_COUNT, false>), dim3(grid), dim3(1024), 0, st, a, S,
+        hipLaunchKernelGGL((k_numeric_global<MODE_COUNT>), dim3(grid), dim3(1024), 0, st, a, S,
                            cap, (char *)slab, slab_bytes);
         break;
     case MODE_EXPAND:
-        hipLaunchKernelGGL((k_numeric_global<MODE_EXPAND, false>), dim3(grid), dim3(1024), 0, st, a, S,
+        hipLaunchKernelGGL((k_numeric_global<MODE_EXPAND>), dim3(grid), dim3(1024), 0, st, a, S,
                            cap, (char *)slab, slab_bytes);
         break;
     case MODE_ITERATE:
-        hipLaunchKernelGGL((k_numeric_global<MODE_ITERATE, false>), dim3(grid), dim3(1024), 0, st, a,
+        hipLaunchKernelGGL((k_numeric_global<MODE_ITERATE>), dim3(grid), dim3(1024), 0, st, a,
                            S, cap, (char *)slab, slab_bytes);
         break;
     }

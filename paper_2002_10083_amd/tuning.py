@@ -42,6 +42,14 @@ def load_policy(key: str, default=(0, 1.0, 5)):
         return default
 
 
+def has_policy(key: str) -> bool:
+    try:
+        with open(TUNED) as f:
+            return key in json.load(f)
+    except (OSError, ValueError):
+        return False
+
+
 def save_policy(key: str, policy: int, scale: float, keys: int, info: dict, path: str = TUNED):
     d = {}
     if os.path.exists(path):
@@ -52,9 +60,27 @@ def save_policy(key: str, policy: int, scale: float, keys: int, info: dict, path
         json.dump(d, f, indent=1, sort_keys=True)
 
 
-def tune(run, reps=2, log=print):
+def candidates_from(key: str, slack: float = 1.3):
+    """Per bin, the variants whose time in the stored tuning of `key` was
+    within `slack` of that bin's best (all variants where none is stored)."""
+    out = [list(range(n)) for n in VARIANTS]
+    try:
+        with open(TUNED) as f:
+            bins = json.load(f)[key]["bins"]
+    except (OSError, KeyError, ValueError):
+        return out
+    for b, times in bins.items():
+        b = int(b)
+        if b < len(out) and len(times) == VARIANTS[b]:
+            best = min(times)
+            out[b] = [v for v, t in enumerate(times) if t <= slack * best]
+    return out
+
+
+def tune(run, reps=2, log=print, candidates=None, scales=SCALES, keys=KEYS):
     """run(policy, scale, keys) -> stats dict of one step (bin_ms, t_total_ms).
-    Returns (policy, scale, keys, report)."""
+    candidates: per bin, the variants to try (default all).  Returns
+    (policy, scale, keys, report)."""
     import torch
 
     def measure(policy, scale, keys=5):
@@ -75,20 +101,21 @@ def tune(run, reps=2, log=print):
     base_ms, base_st = measure(pack(variants), scale)
     report["start_ms"] = base_ms
     for b in range(len(VARIANTS)):
-        times = []
-        for v in range(VARIANTS[b]):
+        cand = candidates[b] if candidates else list(range(VARIANTS[b]))
+        times = {}
+        for v in cand:
             trial = list(variants)
             trial[b] = v
             ms, st = measure(pack(trial), scale)
-            times.append(st["bin_ms"][b])
+            times[v] = st["bin_ms"][b]
         if st["bin_cols"][b] == 0:
             continue
-        variants[b] = min(range(len(times)), key=lambda v: times[v])
-        report["bins"][b] = [round(t, 3) for t in times]
+        variants[b] = min(times, key=lambda v: times[v])
+        report["bins"][b] = [round(times[v], 3) if v in times else None for v in range(VARIANTS[b])]
         log("bin %d variant times %s -> %d" % (b, report["bins"][b], variants[b]))
     best_scale, best_keys, best_ms = scale, 5, None
-    for r in KEYS:
-        for sc in SCALES:
+    for r in keys:
+        for sc in scales:
             ms, st = measure(pack(variants), sc, r)
             log("keys %d scale %.2f: %.1f ms (overflow %d)" % (r, sc, ms, st["n_overflow"]))
             if best_ms is None or ms < best_ms:
