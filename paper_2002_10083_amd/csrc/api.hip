@@ -397,12 +397,15 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
 }
 
 // Runs the numeric phase for the columns binned in `pl`, then resolves table
-// overflow: overflowed columns move one LDS bin up (the largest LDS bin to
-// the multi-pass kernel) and are recomputed into a new temp region; columns
-// that overflow again, or that overflowed the largest table, get an exact
+// overflow.  An overflowed column whose keys the split kernels counted is
+// re-binned by that exact count (smallest LDS bin that holds it, else the
+// multi-pass kernel at that size); any other overflowed column moves one LDS
+// bin up (the largest LDS bin to the multi-pass kernel).  Both are recomputed
+// into a new temp region.  A column that still overflows after its second
+// launch (third, if it was re-binned by its exact count twice) gets an exact
 // count and an HBM table of exactly that size, which cannot overflow.  So
-// every column is launched at most three times whatever its estimate.  `a`
-// carries A/B (or parts), the prune args and the per-column outputs.
+// every column is launched at most four times whatever its estimate.  `a`
+// carries A/B, the prune args and the per-column outputs.
 void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::NumericArgs a,
             ProductPlan &pl, EngineOut &eo, Timer &tm, const int64_t *bcolptr = nullptr,
             uint32_t policy = 0)
@@ -425,6 +428,8 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     }
     a.part_cnt = mem.ws<int32_t>(std::max<int64_t>(n, 1));
     HIPC(hipMemsetAsync(a.part_cnt, 0, std::max<int64_t>(n, 1) * sizeof(int32_t), mem.st));
+    a.exact_cnt = mem.ws<int64_t>(std::max<int64_t>(n, 1));
+    HIPC(hipMemsetAsync(a.exact_cnt, 0xFF, std::max<int64_t>(n, 1) * sizeof(int64_t), mem.st));  // -1
     a.lo = pl.lo;
     a.hi = pl.hi;
     a.hbm_only = pl.hbm_only;
@@ -465,16 +470,18 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         if (round == 1) eo.t_numeric = tm.ms(t0, t1);
         if (novf == 0) break;
         if (round == 1) eo.n_overflow = novf;
-        // at most three rounds reach this point (see above); the region table
+        // at most four rounds reach this point (see above); the region table
         // holds MAX_REGIONS temp regions
         if (round >= mcl::MAX_REGIONS) fail(MCL_EHIP, "table overflow did not resolve");
-        // first round: one bin up (the largest LDS bin to the multi-pass
-        // kernel, or the exact path); later rounds: the exact path
+        // a column whose keys the split kernels counted is re-binned by that
+        // count (first and second round); otherwise the first round moves it
+        // one bin up (the largest LDS bin to the multi-pass kernel) and later
+        // rounds send it to the exact path
         int32_t *counts_d = dev_i + 1;       // 8 counters
         int32_t *nexact_d = dev_i + 9;
         int32_t *exact = mem.ws<int32_t>(novf);
         mcl::launch_bump(ovf, novf, pl.bin, pl.capv, counts_d, exact, nexact_d,
-                         mode != mcl::MODE_COUNT && a.goff, round >= 2, mem.st);
+                         mode != mcl::MODE_COUNT && a.goff, round, a.exact_cnt, mem.st);
         int32_t hc[9];
         HIPC(hipMemcpyAsync(hc, counts_d, 9 * sizeof(int32_t), hipMemcpyDeviceToHost, mem.st));
         HIPC(hipStreamSynchronize(mem.st));

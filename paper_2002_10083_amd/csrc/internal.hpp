@@ -47,6 +47,7 @@ struct NumericArgs {
     uint32_t src_end;         // sliced copy: index of the entry past the last (row -1, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
     int32_t *part_cnt;        // split sliced kernels: keys appended per column (all zero between launches)
+    int64_t *exact_cnt;       // split sliced kernels: exact key count of an overflowed column, -1 = unknown
 };
 
 // ---- spgemm.hip
@@ -99,9 +100,12 @@ void launch_list_bound(const int32_t *list, int32_t n, const int64_t *flops, con
                        const int32_t *hi, int64_t nrows, int64_t *ub, int64_t *max_ub, hipStream_t st);
 void launch_list_base(const int32_t *list, int32_t n, const int64_t *capv, int64_t *base, int64_t *total,
                       int region, hipStream_t st);
+// round 1 and 2: columns with a known exact count (exact_cnt, nullable) are
+// re-binned by it; round 1 moves the others one bin up; later rounds send
+// the rest to the exact path
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, bool force_exact,
-                 hipStream_t st);
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, int round,
+                 const int64_t *exact_cnt, hipStream_t st);
 // acc: per bin {flops, nnz(B_*j), output entries, unpruned product entries (prod, or out_cnt if null)}
 void launch_bin_sums(const int32_t *lists, const BinOffsets &off, const BinOffsets &cnt,
                      const int64_t *flops, const int64_t *bcolptr, const int64_t *out_cnt,

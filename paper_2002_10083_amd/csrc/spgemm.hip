@@ -37,14 +37,12 @@ constexpr int64_t REGION_MASK = ((int64_t)1 << 48) - 1;
 // (load factor 3/4; more keys flag the column as overflowed).
 __host__ __device__ constexpr int bin_slots_c(int b) { return 128 << b; }
 __host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4; }
-// Multi-pass kernel of the largest columns (bin 7): 16 waves with 512-slot
-// tables per pass, 2 or 4 passes.
-constexpr int MP_NW = 16, MP_SW = 512;
-constexpr int MP_CAPW = (13 * MP_SW) / 16;
-// keys a column may be planned with per pass (headroom for the uneven
-// spread of rows over the 16 waves)
-constexpr int64_t MP_PASS_PLAN = (int64_t)MP_NW * MP_CAPW * 4 / 5;
-constexpr int64_t MP_MAX = 4 * MP_PASS_PLAN;
+// Largest columns (bin 7) in LDS: 64 waves per column, one row group each,
+// in concurrent workgroups -- 512-slot tables per wave up to MP_NARROW keys,
+// 1024-slot tables up to MP_MAX (4/5 of the tables' capacity: headroom for
+// an uneven spread of rows over the waves).  Larger columns use HBM tables.
+constexpr int64_t MP_NARROW = (int64_t)64 * ((13 * 512) / 16) * 4 / 5;
+constexpr int64_t MP_MAX = (int64_t)64 * ((13 * 1024) / 16) * 4 / 5;
 // Keys a column may be planned with in bin b: bins of 1024+ slots split the
 // column over waves with private tables, so they keep 1/8 headroom for an
 // uneven spread of rows over the waves.
@@ -589,35 +587,50 @@ __global__ __launch_bounds__(256) void k_bump(const int32_t *__restrict__ list, 
                                               int32_t *__restrict__ bin_count,
                                               int32_t *__restrict__ exact_list,
                                               int32_t *__restrict__ n_exact, int to_multipass,
-                                              int force_exact)
+                                              int round, const int64_t *__restrict__ exact_cnt)
 {
     for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool valid = i < n;
         const int j = valid ? list[i] : 0;
         const int b = valid ? bin[j] : 0;
-        // LDS bins move one up; the largest LDS bin moves to the multi-pass
-        // kernel at its full capacity (when available); the rest go to the
-        // exact count
-        const bool up = valid && !force_exact &&
-                        (b + 1 < NUM_LDS_BINS || (to_multipass && b + 1 == NUM_LDS_BINS));
-        if (up) {
-            bin[j] = b + 1;
-            capv[j] = (b + 1 < NUM_LDS_BINS) ? (int64_t)bin_cap_c(b + 1) : MP_MAX;
+        const int64_t ex = (valid && exact_cnt && round <= 2) ? exact_cnt[j] : -1;
+        int nb = b + 1;
+        bool up;
+        if (ex >= 0) {
+            // the split kernels counted the column's keys: the smallest LDS
+            // bin that holds them, else the multi-pass kernel at that size
+            nb = 0;
+            while (nb < NUM_LDS_BINS && bin_cap_c(nb) < ex) ++nb;
+            up = nb < NUM_LDS_BINS || (to_multipass && ex <= MP_MAX);
+            if (up) {
+                bin[j] = nb;
+                capv[j] = (nb < NUM_LDS_BINS) ? (int64_t)bin_cap_c(nb) : max(ex, (int64_t)1);
+            }
+        } else {
+            // LDS bins move one up; the largest LDS bin moves to the
+            // multi-pass kernel at its full capacity (when available); the
+            // rest go to the exact count
+            up = valid && round == 1 && (b + 1 < NUM_LDS_BINS || (to_multipass && b + 1 == NUM_LDS_BINS));
+            if (up) {
+                bin[j] = b + 1;
+                capv[j] = (b + 1 < NUM_LDS_BINS) ? (int64_t)bin_cap_c(b + 1) : MP_NARROW;
+            }
         }
-        wave_reserve<NUM_LDS_BINS + 1>(bin_count, b + 1, up);
+        wave_reserve<NUM_LDS_BINS + 1>(bin_count, nb, up);
         const int pos = wave_reserve<1>(n_exact, 0, valid && !up);
         if (valid && !up) exact_list[pos] = j;
     }
 }
 
 void launch_bump(const int32_t *list, int32_t n, int32_t *bin, int64_t *capv, int32_t *bin_count,
-                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, bool force_exact, hipStream_t st)
+                 int32_t *exact_list, int32_t *n_exact, bool to_multipass, int round,
+                 const int64_t *exact_cnt, hipStream_t st)
 {
     if (n <= 0) return;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_bump, dim3(grid), dim3(256), 0, st, list, n, bin, capv, bin_count, exact_list,
-                       n_exact, (int)to_multipass, (int)force_exact);
+                       n_exact, (int)to_multipass, round, exact_cnt);
 }
 
 // Per-bin totals of the launched columns: flops, nnz(B_*j), output count.
@@ -1708,13 +1721,23 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
 // XCD (workgroups are dealt to the 8 XCDs in turn), so the column's step
 // metadata is fetched once per L2.
 // ---------------------------------------------------------------------------
-constexpr int32_t PART_OVF = 1 << 30;
+constexpr int32_t PART_OVF = 1 << 30;         // the column does not fit its slot
+constexpr int32_t PART_INC = 1 << 29;         // ... and its key count is incomplete
+constexpr int32_t PART_CNT = PART_INC - 1;    // key count bits
+
+// Overflowed column with a complete count: record it (the overflow round
+// re-plans the column at that size instead of counting it again).
+__device__ __forceinline__ void note_exact(const NumericArgs &a, int64_t j, int32_t c)
+{
+    if (a.exact_cnt && !(c & PART_INC)) a.exact_cnt[j] = c & PART_CNT;
+}
 
 __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j);
 
 // MP: the launch holds the multi-pass columns of the largest bin together
-// with HBM-table columns, which it skips.
-template <int NWP, int SW, int P, int MODE, int D, bool MP = false>
+// with HBM-table columns, which it skips; 1 = the columns of up to MP_NARROW
+// keys, 2 = the larger ones.
+template <int NWP, int SW, int P, int MODE, int D, int MP = 0>
 __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
 {
     constexpr int G = NG / (P * NWP);  // groups per wave
@@ -1736,7 +1759,7 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
     const uint32_t idx = (b / (8 * P)) * 8 + r % 8;
     if (idx >= (uint32_t)a.ncols) return;  // whole workgroup
     const int64_t j = a.cols[idx];
-    if (MP && !multipass_column(a, j)) return;  // whole workgroup
+    if (MP && !(multipass_column(a, j) && (MP == 1) == (a.capv[j] <= MP_NARROW))) return;  // whole workgroup
     if (tid == 0) sh.misc[0] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
@@ -1755,20 +1778,24 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
         ovf |= sh.wovf[q];
     }
     if (tid == 0) {
+        // every part adds its key count, so an overflowed column still gets
+        // its exact count -- unless a wave table overflowed, or the part
+        // alone passed the column's capacity (its waves then stop early)
         int off = -1;
-        if (!ovf) {
+        if (ovf || sh.misc[0] > col_cap) {
+            atomicOr(&a.part_cnt[j], PART_OVF | PART_INC);
+        } else {
             off = atomicAdd(&a.part_cnt[j], mp);
-            if ((off & PART_OVF) || (int64_t)off + mp > col_cap) ovf = 1;
-        }
-        if (ovf) {
-            atomicOr(&a.part_cnt[j], PART_OVF);
-            off = -1;
+            if ((off & PART_OVF) || (int64_t)(off & PART_CNT) + mp > col_cap) {
+                atomicOr(&a.part_cnt[j], PART_OVF);
+                off = -1;
+            }
         }
         sh.misc[1] = off;
     }
     __syncthreads();
-    const int off = sh.misc[1];
-    if (off < 0) return;
+    const int off = sh.misc[1] & PART_CNT;
+    if (sh.misc[1] < 0) return;
     const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
     const int32_t *wkey = sh.key + w * SW;
     const double *wval = sh.val + w * SW;
@@ -1793,13 +1820,20 @@ __global__ __launch_bounds__(NWP * WAVE) void k_numeric_part(NumericArgs a)
     numeric_part_body<NWP, SW, P, MODE, D>(a);
 }
 
-// the multi-pass columns of the largest bin: 64 waves per column, one row group each
-constexpr int MPP_NW = 8, MPP_P = 8;
-static_assert(MPP_NW * MPP_P == NG, "one group per wave");
+// the multi-pass columns of the largest bin: 64 waves per column, one row
+// group each; 8 workgroups of 8 waves with 512-slot tables for columns of up
+// to MP_NARROW keys, 16 workgroups of 4 waves with 1024-slot tables above
+constexpr int MPP_NW = 8, MPP_P = 8, MPW_NW = 4, MPW_P = 16;
+static_assert(MPP_NW * MPP_P == NG && MPW_NW * MPW_P == NG, "one group per wave");
 template <int MODE>
 __global__ __launch_bounds__(MPP_NW * WAVE) void k_numeric_mpart(NumericArgs a)
 {
-    numeric_part_body<MPP_NW, 512, MPP_P, MODE, 2, true>(a);
+    numeric_part_body<MPP_NW, 512, MPP_P, MODE, 2, 1>(a);
+}
+template <int MODE>
+__global__ __launch_bounds__(MPW_NW * WAVE) void k_numeric_mpart_wide(NumericArgs a)
+{
+    numeric_part_body<MPW_NW, 1024, MPW_P, MODE, 2, 2>(a);
 }
 
 template <int NWP, int SW, int P, int MODE, int D>
@@ -1843,7 +1877,10 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
     __syncthreads();  // every thread has read the counter before it is reset
     if (tid == 0) a.part_cnt[j] = 0;
     if (bad) {
-        if (tid == 0) a.out_cnt[j] = -1;
+        if (tid == 0) {
+            a.out_cnt[j] = -1;
+            if (c & PART_OVF) note_exact(a, j, c);
+        }
         return;
     }
     const int m = c;
@@ -1909,11 +1946,10 @@ static void launch_part(const NumericArgs &a, hipStream_t st, hipEvent_t mid)
 }
 
 // ---------------------------------------------------------------------------
-// Columns too large for one LDS table set: P = 2 or 4 passes of 16 waves,
-// pass p covering the row groups [p*64/P, (p+1)*64/P) (disjoint row sets, so
-// every row is accumulated in exactly one pass, in ascending k).  Each pass
-// appends its keys and values, unsorted, to the column's output slot; the
-// finishing kernel below sorts them and runs the epilogue.
+// Columns too large for one LDS table set (bin 7): the split kernels above
+// with 64 waves per column append their keys and values, unsorted, to the
+// column's output slot; the finishing kernel below sorts them and runs the
+// epilogue.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j)
@@ -1921,75 +1957,12 @@ __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j
     return a.goff && a.capv && !(a.hbm_only && a.hbm_only[j]) && a.capv[j] <= MP_MAX;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(MP_NW * WAVE) void k_numeric_mpass(NumericArgs a)
-{
-    constexpr int STOT = MP_NW * MP_SW;
-    struct alignas(16) Sh {
-        double val[STOT];
-        int32_t key[STOT];
-        int32_t wcnt[MP_NW], wovf[MP_NW];
-        int32_t total[4];
-        double dmisc[4];
-    };
-    __shared__ Sh sh __attribute__((aligned(16)));
-    const int tid = threadIdx.x;
-    const int w = tid / WAVE;
-    const int64_t j = a.cols[blockIdx.x];
-    if (!multipass_column(a, j)) return;  // whole workgroup
-    const int64_t capv = a.capv[j];
-    const int P = (capv <= 2 * MP_PASS_PLAN) ? 2 : 4;
-    const int gpw = NG / (MP_NW * P);  // groups per wave and pass
-    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
-    int64_t off = 0;
-    for (int p = 0; p < P; ++p) {
-        const int g0 = p * (NG / P) + w * gpw;
-        int32_t *wkey = sh.key + w * MP_SW;
-        double *wval = sh.val + w * MP_SW;
-        if (tid == 0) sh.total[p & 1] = 0;
-        __syncthreads();
-        const int keys_w = slice_accumulate<MP_SW, MODE, 4>(a, j, g0, g0 + gpw, wkey, wval, &sh.wovf[w],
-                                                            MP_CAPW, &sh.dmisc[3], &sh.total[p & 1], capv - off);
-        if (lane() == 0) {
-            sh.wcnt[w] = keys_w;
-            if (keys_w > MP_CAPW) sh.wovf[w] = 1;
-        }
-        __syncthreads();
-        int mp = 0, ovf = 0, pre = 0;
-        for (int q = 0; q < MP_NW; ++q) {
-            if (q < w) pre += sh.wcnt[q];
-            mp += sh.wcnt[q];
-            ovf |= sh.wovf[q];
-        }
-        if (ovf || off + mp > capv) {
-            if (tid == 0) a.out_cnt[j] = -1;
-            return;
-        }
-        // append this wave's keys (slot order) after the earlier waves and passes
-        int run = 0;
-        for (int s0 = 0; s0 < MP_SW; s0 += WAVE) {
-            const int k = wkey[s0 + lane()];
-            const uint64_t mk = ballot(k != EMPTY_KEY);
-            if (k != EMPTY_KEY) {
-                const int64_t d = base + off + pre + run + popc_below(mk);
-                a.out_row[d] = k;
-                if (MODE != MODE_COUNT) a.out_val[d] = wval[s0 + lane()];
-            }
-            run += __popcll(mk);
-        }
-        off += mp;
-        __syncthreads();  // the next pass clears the tables
-    }
-    if (tid == 0) a.out_cnt[j] = off;
-}
-
 // Finishing pass for the multi-pass columns: copies the m appended entries
-// to HBM scratch, sorts them by row, then writes them (expand) or runs the
-// fused epilogue on them (iterate).  Persistent workgroups with one scratch
-// slab each, like the HBM-table kernel.
-// SPLIT: the entries were appended by k_numeric_mpart (count and overflow
-// flag in part_cnt, reset here) instead of k_numeric_mpass (count in out_cnt).
-template <int MODE, bool SPLIT>
+// (count and overflow flags in part_cnt, reset here) to HBM scratch, sorts
+// them by row, then writes them (expand) or runs the fused epilogue on them
+// (iterate).  Persistent workgroups with one scratch slab each, like the
+// HBM-table kernel.
+template <int MODE>
 __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab, size_t slab_bytes)
 {
     constexpr int NT = 1024;
@@ -2015,20 +1988,17 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
         const int64_t j = a.cols[idx];
         if (!multipass_column(a, j)) continue;
-        int m;
-        if constexpr (SPLIT) {
-            const int c = a.part_cnt[j];
-            __syncthreads();  // every thread has read the counter before it is reset
-            if (tid == 0) a.part_cnt[j] = 0;
-            if ((c & PART_OVF) || c > (int)MP_MAX) {
-                if (tid == 0) a.out_cnt[j] = -1;
-                continue;
+        const int c = a.part_cnt[j];
+        __syncthreads();  // every thread has read the counter before it is reset
+        if (tid == 0) a.part_cnt[j] = 0;
+        if ((c & PART_OVF) || c > (int)MP_MAX) {
+            if (tid == 0) {
+                a.out_cnt[j] = -1;
+                if (c & PART_OVF) note_exact(a, j, c);
             }
-            m = c;
-        } else {
-            if (a.out_cnt[j] < 0) continue;
-            m = (int)a.out_cnt[j];
+            continue;
         }
+        const int m = c;
         const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
         for (int q = tid; q < m; q += NT) {
             skey[q] = a.out_row[base + q];
@@ -2042,7 +2012,7 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
                 a.out_row[base + rank] = skey[s];
                 a.out_val[base + rank] = sval[s];
             });
-            if (SPLIT && tid == 0) a.out_cnt[j] = m;
+            if (tid == 0) a.out_cnt[j] = m;
         } else {
             sort_table<NT, true, int32_t>(skey, m, m, lo, span, bcnt, bcur, NB, list, wsum,
                                           [&](int rank, int s) { sorted[rank] = s; });
@@ -2072,30 +2042,18 @@ size_t mpass_slab_bytes()
 void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
                           hipStream_t st)
 {
-    if (a.ncols <= 0 || !a.goff || mode == MODE_COUNT) return;
+    if (a.ncols <= 0 || !a.goff || !a.part_cnt || mode == MODE_COUNT) return;
     const int grid = std::min(nslabs, a.ncols);
-    const unsigned pgrid = (unsigned)(((a.ncols + 7) / 8) * 8 * MPP_P);
-    const bool split = a.part_cnt != nullptr;
+    const unsigned g8 = (unsigned)(((a.ncols + 7) / 8) * 8);
     if (mode == MODE_EXPAND) {
-        if (split) {
-            hipLaunchKernelGGL(k_numeric_mpart<MODE_EXPAND>, dim3(pgrid), dim3(MPP_NW * WAVE), 0, st, a);
-            hipLaunchKernelGGL((k_finish_mpass<MODE_EXPAND, true>), dim3(grid), dim3(1024), 0, st, a,
-                               (char *)slab, slab_bytes);
-        } else {
-            hipLaunchKernelGGL(k_numeric_mpass<MODE_EXPAND>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
-            hipLaunchKernelGGL((k_finish_mpass<MODE_EXPAND, false>), dim3(grid), dim3(1024), 0, st, a,
-                               (char *)slab, slab_bytes);
-        }
+        hipLaunchKernelGGL(k_numeric_mpart<MODE_EXPAND>, dim3(g8 * MPP_P), dim3(MPP_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_numeric_mpart_wide<MODE_EXPAND>, dim3(g8 * MPW_P), dim3(MPW_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_finish_mpass<MODE_EXPAND>, dim3(grid), dim3(1024), 0, st, a, (char *)slab, slab_bytes);
     } else {
-        if (split) {
-            hipLaunchKernelGGL(k_numeric_mpart<MODE_ITERATE>, dim3(pgrid), dim3(MPP_NW * WAVE), 0, st, a);
-            hipLaunchKernelGGL((k_finish_mpass<MODE_ITERATE, true>), dim3(grid), dim3(1024), 0, st, a,
-                               (char *)slab, slab_bytes);
-        } else {
-            hipLaunchKernelGGL(k_numeric_mpass<MODE_ITERATE>, dim3(a.ncols), dim3(MP_NW * WAVE), 0, st, a);
-            hipLaunchKernelGGL((k_finish_mpass<MODE_ITERATE, false>), dim3(grid), dim3(1024), 0, st, a,
-                               (char *)slab, slab_bytes);
-        }
+        hipLaunchKernelGGL(k_numeric_mpart<MODE_ITERATE>, dim3(g8 * MPP_P), dim3(MPP_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_numeric_mpart_wide<MODE_ITERATE>, dim3(g8 * MPW_P), dim3(MPW_NW * WAVE), 0, st, a);
+        hipLaunchKernelGGL(k_finish_mpass<MODE_ITERATE>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
+                           slab_bytes);
     }
 }
 
