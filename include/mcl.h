@@ -124,6 +124,7 @@ typedef struct {
        unpruned product entries of every bin's columns */
     double bin_part_ms[8];
     int64_t bin_prod[8];
+    int64_t n_dense;          /* columns accumulated in a dense array over their row span */
 } mcl_stats;
 
 /* Fills `p` with the defaults: theta 1e-4, S 1100, R 1400, pct 0.9, r 2,

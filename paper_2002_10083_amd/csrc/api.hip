@@ -247,6 +247,7 @@ struct EngineOut {
     double bin_part_ms[8] = {0};  // split bins: accumulation kernel alone
     int64_t bin_cols[8] = {0};
     int64_t bin_acc[32] = {0};  // per bin: flops, nnz(B_*j), output entries, unpruned entries
+    int64_t n_dense = 0;        // columns computed by the dense-accumulator kernels
     int n_phases = 0;
 };
 
@@ -430,6 +431,15 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     HIPC(hipMemsetAsync(a.part_cnt, 0, std::max<int64_t>(n, 1) * sizeof(int32_t), mem.st));
     a.exact_cnt = mem.ws<int64_t>(std::max<int64_t>(n, 1));
     HIPC(hipMemsetAsync(a.exact_cnt, 0xFF, std::max<int64_t>(n, 1) * sizeof(int64_t), mem.st));  // -1
+    a.dense = nullptr;
+    int64_t *ndense = nullptr;
+    if (a.goff && mode != mcl::MODE_COUNT && n > 0) {
+        uint8_t *dn = mem.ws<uint8_t>(n);
+        ndense = mem.ws<int64_t>(1);
+        HIPC(hipMemsetAsync(ndense, 0, sizeof(int64_t), mem.st));
+        mcl::launch_mark_dense(n, pl.bin, pl.flops, pl.lo, pl.hi, dn, ndense, mem.st);
+        a.dense = dn;
+    }
     a.lo = pl.lo;
     a.hi = pl.hi;
     a.hbm_only = pl.hbm_only;
@@ -450,6 +460,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         mcl::launch_bin_sums(pl.lists, offsets_of(pl.counts), cnt, pl.flops, bcolptr, pl.cnt, a.nnz_prod, acc,
                              mem.st);
         HIPC(hipMemcpyAsync(eo.bin_acc, acc, sizeof(eo.bin_acc), hipMemcpyDeviceToHost, mem.st));
+        if (ndense) HIPC(hipMemcpyAsync(&eo.n_dense, ndense, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
     }
     tm.mark();
     const size_t t1 = tm.ev.size() - 1;
@@ -498,6 +509,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
             HIPC(hipMemcpyAsync(&max_ub, dev_l, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
             HIPC(hipStreamSynchronize(mem.st));
             mcl::NumericArgs c = a;
+            c.dense = nullptr;  // the exact count covers every listed column
             c.capv = nullptr;
             c.out_row = nullptr;
             c.out_val = nullptr;
@@ -558,6 +570,7 @@ void copy_bin_stats(const EngineOut &eo, mcl_stats *s)
         s->bin_prod[b] = eo.bin_acc[4 * b + 3];
         s->bin_part_ms[b] = eo.bin_part_ms[b];
     }
+    s->n_dense = eo.n_dense;
 }
 
 // Symbolic pass + estimate + plan for C = A*B (or the merge of parts).
@@ -912,6 +925,7 @@ int mcl_iterate(const mcl_csc *A, mcl_csc *A_next, const int64_t *comp_ptr, int6
                 outs.push_back({c0, c1, pcp, r, v});
                 eo.n_overflow += e.n_overflow;
                 eo.n_global += e.n_global;
+                eo.n_dense += e.n_dense;
                 eo.t_numeric += e.t_numeric;
                 eo.t_fallback += e.t_fallback;
                 for (int b = 0; b < 8; ++b) {

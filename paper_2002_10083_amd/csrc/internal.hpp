@@ -48,6 +48,7 @@ struct NumericArgs {
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
     int32_t *part_cnt;        // split sliced kernels: keys appended per column (all zero between launches)
     int64_t *exact_cnt;       // split sliced kernels: exact key count of an overflowed column, -1 = unknown
+    const uint8_t *dense;     // columns computed by the dense-accumulator kernel (or null)
 };
 
 // ---- spgemm.hip
@@ -116,6 +117,9 @@ struct TempRegions {
     const double *val[MAX_REGIONS];
 };
 // mid (nullable): recorded between the accumulation and finishing kernels of a split launch
+// dense-accumulator columns: marked after planning, launched with bins 3..7
+void launch_mark_dense(int64_t ncols, const int32_t *bin, const int64_t *flops, const int32_t *lo,
+                       const int32_t *hi, uint8_t *dense, int64_t *count, hipStream_t st);
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,
                         hipEvent_t mid = nullptr);
 int lds_bin_variants(int bin);

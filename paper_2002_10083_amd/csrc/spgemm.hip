@@ -43,6 +43,12 @@ __host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4
 // an uneven spread of rows over the waves).  Larger columns use HBM tables.
 constexpr int64_t MP_NARROW = (int64_t)64 * ((13 * 512) / 16) * 4 / 5;
 constexpr int64_t MP_MAX = (int64_t)64 * ((13 * 1024) / 16) * 4 / 5;
+// Largest row span of a dense-accumulator column (see k_numeric_dense).
+constexpr int DENSE_SPAN = 8192;
+__host__ __device__ constexpr bool dense_shape(int64_t flops, int64_t span)
+{
+    return flops > 0 && span <= DENSE_SPAN && flops >= 2 * span;
+}
 // Keys a column may be planned with in bin b: bins of 1024+ slots split the
 // column over waves with private tables, so they keep 1/8 headroom for an
 // uneven spread of rows over the waves.
@@ -385,7 +391,9 @@ __global__ __launch_bounds__(256) void k_plan(int64_t ncols, const int64_t *__re
         ub = min(ub, nrows);
         int64_t need = ub;
         bool try_lds = false;
-        if (est_kind != 0 && est && ub > plan_cap_c(2)) {
+        // a column for the dense accumulator is sized by its row span (exact-safe)
+        const bool dense = fl > 0 && dense_shape(fl, (int64_t)(hi[j] - lo[j] + 1));
+        if (est_kind != 0 && est && ub > plan_cap_c(2) && !dense) {
             double e = ceil(1.3 * est_scale * (double)est[j]);
             if (e < 1.0) e = 1.0;
             need = min(ub, (int64_t)e);
@@ -1047,9 +1055,9 @@ __device__ void sort_table(const int32_t *tkey, int S, int m, int32_t lo, int64_
 // sc.sorted: prune (Alg. 1), inflation with column re-normalisation, the
 // change against the previous iterate (column j of B, which is A), and the
 // per-column outputs.  find(row) returns the slot of a row or -1.
-template <int NT, bool GS, typename IdxT, typename Find>
+template <int NT, bool GS, typename IdxT, typename Find, typename Keys = const int32_t *>
 __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t bs, int mj,
-                                 int64_t base, const int32_t *tkey, double *tval,
+                                 int64_t base, Keys tkey, double *tval,
                                  const Scratch<IdxT> &sc, Find find)
 {
     const int tid = threadIdx.x % NT;
@@ -1140,6 +1148,9 @@ __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t
         if (a.mode) a.mode[j] = (int8_t)pmode;
     }
 }
+
+// columns computed by the dense-accumulator kernel (the other kernels skip them)
+__device__ __forceinline__ bool dense_column(const NumericArgs &a, int64_t j) { return a.dense && a.dense[j]; }
 
 // The numeric body for one column j, executed by NT threads.
 template <int NT, int MODE, int E, int D, typename IdxT, bool GS, bool PIPE = false>
@@ -1380,6 +1391,7 @@ __global__ __launch_bounds__(NW * WAVE * CPW) void k_numeric_lds(NumericArgs a)
     Scratch<uint16_t> sc{c.key, c.val, c.list, c.sorted, c.bcnt, c.bcur, c.p0, c.p1,
                          c.ip, c.hist, c.misc, c.dmisc, c.wsum};
     constexpr int logS = __builtin_ctz(S);
+    if (dense_column(a, a.cols[idx])) return;  // whole column group (a workgroup when NW > 1)
     column_body<NT, MODE, E, D, uint16_t, false, PIPE>(a, a.cols[idx], S, logS, L::CAP, L::NB, sc);
 }
 
@@ -1456,17 +1468,26 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *
 // column's key capacity; a wave stops soon after the column total exceeds it
 // (the total is read with the next group's bucket reads, so no LDS round
 // trip waits on it).
-template <int SW, int MODE, int D>
+//
+// DENSE: instead of a hash table, the wave adds into wval[row - dlo] (a
+// dense accumulator over the column's row span, shared by the column's
+// waves, which own disjoint rows, cleared by the caller) and marks the row
+// in the bitmap dbits; wkey, wovf, col_keys and the capacities are unused
+// and the return value is 0.
+template <int SW, int MODE, int D, bool DENSE = false>
 __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1, int32_t *wkey, double *wval,
-                                int *wovf, int capw, double *never, int *col_keys, int64_t col_cap)
+                                int *wovf, int capw, double *never, int *col_keys, int64_t col_cap,
+                                int32_t dlo = 0, uint32_t *dbits = nullptr)
 {
     constexpr int NBW = SW / 4;
     constexpr int LOGNBW = __builtin_ctz(NBW);
-    for (int s = lane(); s < SW; s += WAVE) {
-        wkey[s] = EMPTY_KEY;
-        if (MODE != MODE_COUNT) wval[s] = 0.0;
+    if constexpr (!DENSE) {
+        for (int s = lane(); s < SW; s += WAVE) {
+            wkey[s] = EMPTY_KEY;
+            if (MODE != MODE_COUNT) wval[s] = 0.0;
+        }
+        group_sync<WAVE>();
     }
-    group_sync<WAVE>();
 
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
@@ -1560,7 +1581,24 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 if (MODE != MODE_COUNT) G.vv[i] = ldg(a.sval + (uint64_t)ad);
             }
         };
-        auto fold = [&](Grp &G) {
+        auto fold_dense = [&](Grp &G) {
+            double prod[D];
+            int sl[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                sl[i] = (G.rr[i] != EMPTY_KEY) ? G.rr[i] - dlo : -1;
+                prod[i] = G.vv[i] * G.bb[i];
+                sinkh |= __double2hiint(prod[i]);  // keeps the value load out of the branch
+                // a touched row holds a positive sum unless every product
+                // added to it underflowed to zero: only those mark the bitmap
+                if (sl[i] >= 0 && prod[i] == 0.0) atomicOr(&dbits[sl[i] >> 5], 1u << (sl[i] & 31));
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                for (int q = 0; q < G.nsub[i]; ++q)
+                    if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod[i]);
+        };
+        auto fold_hash = [&](Grp &G) {
             uint32_t hb[D];
             keys4 kb[D];
 #pragma unroll
@@ -1604,6 +1642,10 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             }
             overflow = ballot(lovf != 0) != 0 || keys_w > capw || col_over;
         };
+        auto fold = [&](Grp &G) {
+            if constexpr (DENSE) fold_dense(G);
+            else fold_hash(G);
+        };
         Grp GA, GB;
         issue(GA, 0);
         for (int c0 = 0; c0 < nchunk && !overflow; c0 += 2 * D) {
@@ -1619,8 +1661,10 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         }
         if (next_runs) run_of(kn, wsn, lenn);
     }
-    const bool any_ovf = ballot(lovf != 0) != 0;
-    if (lane() == 0) *wovf = any_ovf ? 1 : 0;
+    if constexpr (!DENSE) {
+        const bool any_ovf = ballot(lovf != 0) != 0;
+        if (lane() == 0) *wovf = any_ovf ? 1 : 0;
+    }
     if (MODE != MODE_COUNT && sinkh < 0) *never = 1.0;  // never: products are >= 0
     group_sync<WAVE>();
     return keys_w;
@@ -1656,6 +1700,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     const int64_t j = a.cols[blockIdx.x];
+    if (dense_column(a, j)) return;  // whole workgroup
     if (tid == 0) sh.misc[8] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? min((int64_t)CAPT, a.capv[j]) : (int64_t)CAPT;
@@ -1734,6 +1779,7 @@ __device__ __forceinline__ void note_exact(const NumericArgs &a, int64_t j, int3
 
 __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j);
 
+
 // MP: the launch holds the multi-pass columns of the largest bin together
 // with HBM-table columns, which it skips; 1 = the columns of up to MP_NARROW
 // keys, 2 = the larger ones.
@@ -1759,7 +1805,8 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
     const uint32_t idx = (b / (8 * P)) * 8 + r % 8;
     if (idx >= (uint32_t)a.ncols) return;  // whole workgroup
     const int64_t j = a.cols[idx];
-    if (MP && !(multipass_column(a, j) && (MP == 1) == (a.capv[j] <= MP_NARROW))) return;  // whole workgroup
+    if (dense_column(a, j)) return;  // whole workgroup
+    if (MP && !(multipass_column(a, j) && (MP == 1) == (a.capv[j] <= MP_NARROW))) return;
     if (tid == 0) sh.misc[0] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
@@ -1871,6 +1918,7 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
     __shared__ Sh sh __attribute__((aligned(16)));
     const int tid = threadIdx.x;
     const int64_t j = a.cols[blockIdx.x];
+    if (dense_column(a, j)) return;  // whole workgroup
     const int c = a.part_cnt[j];
     const bool bad = (c & PART_OVF) || c > mhi;
     if (bad ? !last : (c <= mlo || c > mhi)) return;  // another launch's column (whole workgroup)
@@ -1946,6 +1994,157 @@ static void launch_part(const NumericArgs &a, hipStream_t st, hipEvent_t mid)
 }
 
 // ---------------------------------------------------------------------------
+// Dense accumulator: a column whose product rows span at most SPAN
+// consecutive rows (lo_j .. hi_j from the symbolic pass) and that does at
+// least two multiply-adds per row of that span is accumulated in an LDS
+// array indexed by row - lo_j instead of a hash table: no probing, and the
+// occupied rows come out in ascending order from a bitmap, so the column
+// needs no sort.  As in the sliced-table kernels, wave w owns the rows of
+// the hash groups [w*G, (w+1)*G), so a row's products arrive in ascending k
+// from one wave.  The number of distinct rows is exact, so a column that
+// does not fit its planned slot reports its exact count.
+// ---------------------------------------------------------------------------
+template <int NW, int SPAN, int MODE>
+__global__ __launch_bounds__(NW * WAVE) void k_numeric_dense(NumericArgs a, int span_min)
+{
+    constexpr int NT = NW * WAVE;
+    constexpr int G = NG / NW;
+    constexpr int NWORD = SPAN / 32;
+    constexpr int NBLK = SPAN / WAVE + 2;
+    struct alignas(16) Sh {
+        double acc[SPAN];
+        uint32_t bits[NWORD];
+        int32_t wcnt[NWORD];
+        uint16_t sorted[SPAN], list[SPAN];
+        double p0[NBLK], p1[NBLK];
+        int32_t ip[NBLK];
+        int32_t hist[256];
+        int32_t misc[16];
+        double dmisc[4];
+        int32_t wsum[NW];
+    };
+    __shared__ Sh sh __attribute__((aligned(16)));
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    const int64_t j = a.cols[blockIdx.x];
+    if (!dense_column(a, j)) return;  // whole workgroup
+    const int32_t lo = a.lo[j];
+    const int span = a.hi[j] - lo + 1;
+    if (span > SPAN || span <= span_min) return;  // the other size's column
+    const int nword = (span + 31) / 32;
+    for (int s = tid; s < span; s += NT) sh.acc[s] = 0.0;
+    for (int q = tid; q < nword; q += NT) sh.bits[q] = 0u;
+    __syncthreads();
+    slice_accumulate<512, MODE, 2, true>(a, j, w * G, (w + 1) * G, nullptr, sh.acc, nullptr, 0, &sh.dmisc[3],
+                                         nullptr, 0, lo, sh.bits);
+    __syncthreads();
+    // occupancy: a nonzero sum, or a row whose products all underflowed;
+    // each wave takes 64 consecutive slots per step (two bitmap words)
+    for (int s0 = tid - lane(); s0 < span; s0 += NT) {
+        const int s = s0 + lane();
+        const uint64_t nz = ballot(s < span && sh.acc[s] != 0.0);
+        if (lane() == 0) {
+            sh.bits[s0 >> 5] |= (uint32_t)nz;
+            if ((s0 >> 5) + 1 < nword) sh.bits[(s0 >> 5) + 1] |= (uint32_t)(nz >> 32);
+        }
+    }
+    __syncthreads();
+    // occupied rows in ascending order: word counts, their prefix, then the
+    // set bits of every word
+    for (int q = tid; q < nword; q += NT) sh.wcnt[q] = __popc(sh.bits[q]);
+    __syncthreads();
+    const int m = block_exscan<NT>(sh.wcnt, nword, sh.wsum);
+    const int64_t cap = a.capv ? a.capv[j] : (int64_t)span;
+    if (m > cap) {
+        if (tid == 0) {
+            a.out_cnt[j] = -1;
+            if (a.exact_cnt) a.exact_cnt[j] = m;
+        }
+        return;
+    }
+    for (int q = tid; q < nword; q += NT) {
+        uint32_t b = sh.bits[q];
+        int pos = sh.wcnt[q];
+        while (b) {
+            const int t = __ffs(b) - 1;
+            sh.sorted[pos++] = (uint16_t)(q * 32 + t);
+            b &= b - 1;
+        }
+    }
+    __syncthreads();
+    const int64_t base = a.out_base[j] >= 0 ? a.out_base[j] : ((-a.out_base[j] - 1) & REGION_MASK);
+    if (MODE == MODE_EXPAND) {
+        for (int i = tid; i < m; i += NT) {
+            const int s = sh.sorted[i];
+            a.out_row[base + i] = lo + s;
+            a.out_val[base + i] = sh.acc[s];
+        }
+        if (tid == 0) a.out_cnt[j] = m;
+        return;
+    }
+    struct RowOf {
+        int32_t lo;
+        __device__ int32_t operator[](int s) const { return lo + s; }
+    };
+    Scratch<uint16_t> sc{nullptr, sh.acc, sh.list, sh.sorted, nullptr, nullptr, sh.p0, sh.p1,
+                         sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
+    const int64_t bs = a.B.colptr[j];
+    const int mj = (int)(a.B.colptr[j + 1] - bs);
+    iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, RowOf{lo}, sh.acc, sc, [&](int32_t k) {
+        const int s = k - lo;
+        return (s >= 0 && s < span && ((sh.bits[s >> 5] >> (s & 31)) & 1u)) ? s : -1;
+    });
+}
+
+// Dense launches over a bin's column list: spans up to 4096 rows with 8
+// waves (three workgroups per CU), up to DENSE_SPAN with 16.
+void launch_numeric_dense(NumericMode mode, const NumericArgs &a, hipStream_t st)
+{
+    if (a.ncols <= 0 || !a.dense || !a.goff || mode == MODE_COUNT) return;
+    const unsigned n = (unsigned)a.ncols;
+    if (mode == MODE_EXPAND) {
+        hipLaunchKernelGGL((k_numeric_dense<8, 4096, MODE_EXPAND>), dim3(n), dim3(8 * WAVE), 0, st, a, 0);
+        hipLaunchKernelGGL((k_numeric_dense<16, DENSE_SPAN, MODE_EXPAND>), dim3(n), dim3(16 * WAVE), 0, st, a,
+                           4096);
+    } else {
+        hipLaunchKernelGGL((k_numeric_dense<8, 4096, MODE_ITERATE>), dim3(n), dim3(8 * WAVE), 0, st, a, 0);
+        hipLaunchKernelGGL((k_numeric_dense<16, DENSE_SPAN, MODE_ITERATE>), dim3(n), dim3(16 * WAVE), 0, st, a,
+                           4096);
+    }
+}
+
+// Columns for the dense kernels: planned in bin 3 or above, row span of at
+// most DENSE_SPAN rows and at least two multiply-adds per row of the span
+// (dense_shape; such columns are planned by their span, so they fit).
+__global__ __launch_bounds__(256) void k_mark_dense(int64_t ncols, const int32_t *__restrict__ bin,
+                                                    const int64_t *__restrict__ flops,
+                                                    const int32_t *__restrict__ lo, const int32_t *__restrict__ hi,
+                                                    uint8_t *__restrict__ dense,
+                                                    unsigned long long *__restrict__ count)
+{
+    int64_t c = 0;
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = j0 + threadIdx.x;
+        if (j < ncols) {
+            const bool d = bin[j] >= 3 && dense_shape(flops[j], (int64_t)hi[j] - lo[j] + 1);
+            dense[j] = d ? 1 : 0;
+            c += d ? 1 : 0;
+        }
+    }
+    c = wave_sum_i64(c);
+    if (lane() == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+void launch_mark_dense(int64_t ncols, const int32_t *bin, const int64_t *flops, const int32_t *lo,
+                       const int32_t *hi, uint8_t *dense, int64_t *count, hipStream_t st)
+{
+    if (ncols <= 0) return;
+    const unsigned g = (unsigned)std::min<int64_t>((ncols + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_mark_dense, dim3(g), dim3(256), 0, st, ncols, bin, flops, lo, hi, dense,
+                       (unsigned long long *)count);
+}
+
+// ---------------------------------------------------------------------------
 // Columns too large for one LDS table set (bin 7): the split kernels above
 // with 64 waves per column append their keys and values, unsorted, to the
 // column's output slot; the finishing kernel below sorts them and runs the
@@ -1987,7 +2186,7 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
     const int tid = threadIdx.x;
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
         const int64_t j = a.cols[idx];
-        if (!multipass_column(a, j)) continue;
+        if (!multipass_column(a, j) || dense_column(a, j)) continue;
         const int c = a.part_cnt[j];
         __syncthreads();  // every thread has read the counter before it is reset
         if (tid == 0) a.part_cnt[j] = 0;
@@ -2043,6 +2242,7 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
                           hipStream_t st)
 {
     if (a.ncols <= 0 || !a.goff || !a.part_cnt || mode == MODE_COUNT) return;
+    launch_numeric_dense(mode, a, st);
     const int grid = std::min(nslabs, a.ncols);
     const unsigned g8 = (unsigned)(((a.ncols + 7) / 8) * 8);
     if (mode == MODE_EXPAND) {
@@ -2154,6 +2354,7 @@ int lds_bin_variants(int bin)
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,
                         hipEvent_t mid)
 {
+    if (bin >= 3 && a.dense && mode != MODE_COUNT) launch_numeric_dense(mode, a, st);
     if (lds_variant_split(bin, variant) && !a.part_cnt) variant = 0;
     if (lds_variant_sliced(bin, variant) && !a.goff) variant = shared_table_variant(bin);
     switch (mode) {
@@ -2213,7 +2414,7 @@ __global__ __launch_bounds__(1024) void k_numeric_global(NumericArgs a, int S, i
     for (int64_t idx = blockIdx.x; idx < a.ncols; idx += gridDim.x) {
         const int64_t j = a.cols[idx];
         // columns of the multi-pass LDS kernel are done there (not in count mode)
-        if (MODE != MODE_COUNT && multipass_column(a, j)) continue;
+        if (MODE != MODE_COUNT && (multipass_column(a, j) || dense_column(a, j))) continue;
         column_body<NT, MODE, 1, 2, int32_t, true>(a, j, S, logS, cap, NB, sc);
         __syncthreads();
     }

@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("bin_cols", ctypes.c_int64 * 8), ("bin_ms", ctypes.c_double * 8),
                 ("bin_flops", ctypes.c_int64 * 8), ("bin_bnnz", ctypes.c_int64 * 8),
                 ("bin_out", ctypes.c_int64 * 8), ("n_phases", ctypes.c_int64),
-                ("bin_part_ms", ctypes.c_double * 8), ("bin_prod", ctypes.c_int64 * 8)]
+                ("bin_part_ms", ctypes.c_double * 8), ("bin_prod", ctypes.c_int64 * 8),
+                ("n_dense", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}

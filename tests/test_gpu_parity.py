@@ -498,3 +498,23 @@ def test_phased_iterate_matches_oracle(mcl):
     for pb in (3 << 20, 400 << 10):
         _, _, st = check_iterate(mcl, A, phase_bytes=pb)
         assert st["n_phases"] > 1
+
+
+def test_dense_accumulator_columns_match_oracle(mcl):
+    """Components with contiguous vertex ids: product columns whose rows span
+    at most 8,192 consecutive rows and that do at least two multiply-adds per
+    row of the span go to the dense accumulator (a 9,000-vertex component stays
+    on the hash tables).  Two fused iterations, the second from the oracle's
+    first iterate (denser columns), and the plain product equal the oracle."""
+    U = planted_components([6000, 3000, 1500, 400, 9000, 120], [60, 30, 15, 4, 90, 2], s_cap=600, seed=77)
+    A = oracle.normalize(U)
+    _, _, st = check_iterate(mcl, A)
+    assert st["n_dense"] > 0
+    A1, _ = oracle.iterate(A)
+    _, _, st1 = check_iterate(mcl, A1)
+    assert st1["n_dense"] > 0
+    E, _ = mcl.expand(up(mcl, A1), up(mcl, A1))
+    ref = oracle.expand(A1, A1)[0]
+    e = E.to_host()
+    assert np.array_equal(e.colptr, ref.colptr) and np.array_equal(e.rowidx, ref.rowidx)
+    assert np.array_equal(e.val, ref.val)
