@@ -32,7 +32,7 @@ BYTES_PER_FLOP, BYTES_PER_BNZ, BYTES_PER_OUT, BYTES_PER_COL = 12, 28, 12, 8
 
 
 COPY_BYTES = 1 << 30
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_numeric_lds_cfg1.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_numeric_part_cfg1.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_10083_amd", "csrc", "spgemm.hip")
 
 
