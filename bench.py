@@ -571,6 +571,10 @@ def main():
         "numeric_phase_GBps": round(total_bytes / (numeric_ms * 1e-3) / 1e9, 1),
         "roofline": roof,
     }
+    out["bins"] = [{"bin": b, "cols": sts[0]["bin_cols"][b], "flops": sts[0]["bin_flops"][b],
+                    "ms": round(mean_ms[b], 3), "accum_ms": round(part_ms[b], 3),
+                    "algorithmic_GBps": round(bin_bytes(sts[0], b) / max(mean_ms[b], 1e-9) / 1e6, 1)}
+                   for b in range(nb)]
     log("bins ms:", [round(x, 2) for x in mean_ms])
     log("split accumulation ms:", [round(x, 2) for x in part_ms])
     if not args.no_cpu_baseline:

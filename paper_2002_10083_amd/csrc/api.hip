@@ -261,9 +261,13 @@ mcl::BinOffsets offsets_of(const int32_t counts[8])
 
 // Launch every non-empty bin; per-bin times are accumulated into eo.bin_ms
 // when `timed` (events around each launch, on the stream).
+// dense_bin (nullable): dense-accumulator columns per bin; a bin without any
+// skips the dense launches (null: every bin runs them when a.dense is set).
 void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t counts[8],
-              const int32_t *lists, int64_t max_global, EngineOut &eo, bool timed, uint32_t policy = 0)
+              const int32_t *lists, int64_t max_global, EngineOut &eo, bool timed, uint32_t policy = 0,
+              const int64_t *dense_bin = nullptr)
 {
+    const uint8_t *dense_all = a.dense;
     int32_t off = 0;
     std::vector<hipEvent_t> ev;
     std::vector<int> evbin;
@@ -273,6 +277,7 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
         if (c > 0) {
             a.cols = lists + off;
             a.ncols = c;
+            a.dense = (dense_bin && dense_bin[b] == 0) ? nullptr : dense_all;
             hipEvent_t e0 = nullptr, e1 = nullptr, em = nullptr;
             int variant = 0;
             if (b < mcl::NUM_LDS_BINS) {
@@ -431,14 +436,19 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     HIPC(hipMemsetAsync(a.part_cnt, 0, std::max<int64_t>(n, 1) * sizeof(int32_t), mem.st));
     a.exact_cnt = mem.ws<int64_t>(std::max<int64_t>(n, 1));
     HIPC(hipMemsetAsync(a.exact_cnt, 0xFF, std::max<int64_t>(n, 1) * sizeof(int64_t), mem.st));  // -1
+    // dense-accumulator columns, counted per bin: bins without any skip the
+    // dense launches in the first pass
     a.dense = nullptr;
-    int64_t *ndense = nullptr;
+    int64_t dense_bin[8] = {0};
     if (a.goff && mode != mcl::MODE_COUNT && n > 0) {
         uint8_t *dn = mem.ws<uint8_t>(n);
-        ndense = mem.ws<int64_t>(1);
-        HIPC(hipMemsetAsync(ndense, 0, sizeof(int64_t), mem.st));
-        mcl::launch_mark_dense(n, pl.bin, pl.flops, pl.lo, pl.hi, dn, ndense, mem.st);
-        a.dense = dn;
+        int64_t *dc = mem.ws<int64_t>(8);
+        HIPC(hipMemsetAsync(dc, 0, 8 * sizeof(int64_t), mem.st));
+        mcl::launch_mark_dense(n, pl.bin, pl.flops, pl.lo, pl.hi, dn, dc, mem.st);
+        HIPC(hipMemcpyAsync(dense_bin, dc, sizeof(dense_bin), hipMemcpyDeviceToHost, mem.st));
+        HIPC(hipStreamSynchronize(mem.st));
+        for (int b = 0; b < 8; ++b) eo.n_dense += dense_bin[b];
+        if (eo.n_dense > 0) a.dense = dn;
     }
     a.lo = pl.lo;
     a.hi = pl.hi;
@@ -450,7 +460,7 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
     a.out_cnt = pl.cnt;
     tm.mark();
     const size_t t0 = tm.ev.size() - 1;
-    run_bins(mem, mode, a, pl.counts, pl.lists, pl.max_global, eo, true, policy);
+    run_bins(mem, mode, a, pl.counts, pl.lists, pl.max_global, eo, true, policy, dense_bin);
     // per-bin totals of the first pass (the launch shape the timing refers to)
     {
         int64_t *acc = mem.ws<int64_t>(32);
@@ -460,7 +470,6 @@ void engine(Mem &mem, int64_t n, int64_t nrows, mcl::NumericMode mode, mcl::Nume
         mcl::launch_bin_sums(pl.lists, offsets_of(pl.counts), cnt, pl.flops, bcolptr, pl.cnt, a.nnz_prod, acc,
                              mem.st);
         HIPC(hipMemcpyAsync(eo.bin_acc, acc, sizeof(eo.bin_acc), hipMemcpyDeviceToHost, mem.st));
-        if (ndense) HIPC(hipMemcpyAsync(&eo.n_dense, ndense, sizeof(int64_t), hipMemcpyDeviceToHost, mem.st));
     }
     tm.mark();
     const size_t t1 = tm.ev.size() - 1;

@@ -118,6 +118,7 @@ struct TempRegions {
 };
 // mid (nullable): recorded between the accumulation and finishing kernels of a split launch
 // dense-accumulator columns: marked after planning, launched with bins 3..7
+// count: 8 counters (zeroed by the caller), dense columns per planned bin
 void launch_mark_dense(int64_t ncols, const int32_t *bin, const int64_t *flops, const int32_t *lo,
                        const int32_t *hi, uint8_t *dense, int64_t *count, hipStream_t st);
 void launch_numeric_lds(int bin, int variant, NumericMode mode, const NumericArgs &a, hipStream_t st,

@@ -2122,17 +2122,20 @@ __global__ __launch_bounds__(256) void k_mark_dense(int64_t ncols, const int32_t
                                                     uint8_t *__restrict__ dense,
                                                     unsigned long long *__restrict__ count)
 {
-    int64_t c = 0;
+    // count[b]: dense columns planned in bin b
     for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x; j0 < ncols; j0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = j0 + threadIdx.x;
+        int b = -1;
         if (j < ncols) {
             const bool d = bin[j] >= 3 && dense_shape(flops[j], (int64_t)hi[j] - lo[j] + 1);
             dense[j] = d ? 1 : 0;
-            c += d ? 1 : 0;
+            if (d) b = bin[j];
+        }
+        for (int q = 3; q <= NUM_LDS_BINS; ++q) {
+            const uint64_t m = ballot(b == q);
+            if (m && lane() == __ffsll((long long)m) - 1) atomicAdd(&count[q], (unsigned long long)__popcll(m));
         }
     }
-    c = wave_sum_i64(c);
-    if (lane() == 0 && c) atomicAdd(count, (unsigned long long)c);
 }
 
 void launch_mark_dense(int64_t ncols, const int32_t *bin, const int64_t *flops, const int32_t *lo,
