@@ -255,6 +255,43 @@ int mcl_mlp_init(float *state, uint64_t seed, void *stream);
 int mcl_mlp_train_step(float *state, void *packed, const float *feat, const float *target,
                        int64_t rows, float lr, float *loss, float *grad_out, void *stream);
 
+/* Multithreaded CPU hash SpGEMM, the paper's host expansion (Section 6
+ * "Faster SpGEMM on CPU"): C = A*B, unpruned, with HOST matrices.  Every
+ * worker thread keeps one hash table for its lifetime (sized for the largest
+ * column it has met); a symbolic pass counts each output column, a numeric
+ * pass accumulates and sorts it by row.  Products are accumulated in the
+ * library's order (ascending k, product rounded before the addition), so C
+ * is bit-identical to mcl_expand's.  nthreads <= 0 uses every hardware
+ * thread.  A, B: host arrays, read only; every call checks their structure
+ * (colptr[0] == 0, non-decreasing colptr, colptr[ncols] == nnz, rows in
+ * range) -- MCL_EINVAL otherwise, or for A.ncols != B.nrows.  C receives
+ * malloc'd host arrays that the caller releases with mcl_host_free.  stats
+ * (nullable): flops, nnz_product = nnz_kept = nnz(C), t_symbolic_ms,
+ * t_numeric_ms, t_total_ms; the other fields are zero.  MCL_ENOMEM when host
+ * memory runs out (nothing is leaked, C is zeroed). */
+int mcl_expand_host(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int32_t nthreads, mcl_stats *stats);
+
+/* Releases the host arrays of a matrix returned by mcl_expand_host or
+ * mcl_expand_dispatch and zeroes its pointers and nnz. */
+void mcl_host_free(mcl_csc *C);
+
+/* Where a product of HOST matrices runs, chosen by its flops (Section 3
+ * "Pipelined Sparse SUMMA": a multiplication with too few operations to
+ * occupy the GPU stays on the CPU): flops(A*B) < gpu_min_flops runs
+ * mcl_expand_host on nthreads threads; otherwise A and B are copied to the
+ * device (arrays from `alloc` on `stream`), multiplied by mcl_expand with
+ * `params`, and C is copied back.  gpu_min_flops <= 0 selects
+ * MCL_DISPATCH_GPU_MIN_FLOPS, the crossover measured on one MI355X with its
+ * host (GPU time including both copies vs 16 host threads).  Either way C
+ * holds malloc'd host arrays (release with mcl_host_free) and is
+ * bit-identical.  where (nullable) receives 0 (CPU) or 1 (GPU); stats as in
+ * mcl_expand_host or mcl_expand, with t_total_ms covering the whole call
+ * (copies included).  Errors as in mcl_expand_host and mcl_expand. */
+#define MCL_DISPATCH_GPU_MIN_FLOPS 16000000
+int mcl_expand_dispatch(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int64_t gpu_min_flops,
+                        int32_t nthreads, const mcl_params *params, const mcl_allocator *alloc,
+                        void *stream, mcl_stats *stats, int32_t *where);
+
 /* Thread-local text of the last error. */
 const char *mcl_last_error(void);
 

@@ -2,11 +2,13 @@
 // through the caller's stream-ordered allocator, and the orchestration of the
 // symbolic / estimate / plan / numeric / fallback / compaction kernels.
 #include "mcl.h"
+#include "host_spgemm.hpp"
 #include "internal.hpp"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -389,15 +391,18 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
     const int64_t nz = a.A.nnz;
     int32_t *ro = mem.ws<int32_t>(nz + 1);
     double *vo = mem.ws<double>(nz + 1);
+    uint32_t *rec = mem.ws<uint32_t>(3 * (nz + 1));
     int32_t *go = mem.ws<int32_t>(a.A.ncols * (mcl::SLICE_GROUPS + 1));
     HIPC(hipMemsetAsync(ro + nz, 0xFF, sizeof(int32_t), mem.st));
     HIPC(hipMemsetAsync(vo + nz, 0, sizeof(double), mem.st));
-    mcl::launch_slice_layout(a.A, ro, vo, go, mem.st);
-    // every kernel reads the sliced copy (same columns, rows grouped by hash)
+    HIPC(hipMemsetAsync(rec + 3 * nz, 0xFF, sizeof(uint32_t), mem.st));
+    HIPC(hipMemsetAsync(rec + 3 * nz + 1, 0, 2 * sizeof(uint32_t), mem.st));
+    mcl::launch_slice_layout(a.A, ro, vo, rec, go, mem.st);
+    // every kernel reads the sliced copy (same columns, rows grouped by hash):
+    // the sliced-table kernels as packed records, the others as arrays
     a.A.rowidx = ro;
     a.A.val = vo;
-    a.srow = ro;
-    a.sval = vo;
+    a.srec = rec;
     a.goff = go;
     a.src_end = (uint32_t)nz;
 }
@@ -1285,6 +1290,158 @@ int mcl_mlp_train_step(float *state, void *packed, const float *feat, const floa
     });
     mem.free_work();
     if (rc != MCL_OK) (void)hipStreamSynchronize((hipStream_t)stream);
+    return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Host hash SpGEMM and the CPU/GPU dispatch (host matrices)
+// ---------------------------------------------------------------------------
+namespace {
+
+mcl::host::CSC host_csc(const mcl_csc *m, const char *name)
+{
+    if (!m) fail(MCL_EINVAL, std::string(name) + " is NULL");
+    if (m->nrows >= (int64_t)INT32_MAX || m->ncols >= (int64_t)INT32_MAX)
+        fail(MCL_EINVAL, std::string(name) + ": dimensions must be < 2^31");
+    mcl::host::CSC h{m->nrows, m->ncols, m->nnz, m->colptr, m->rowidx, m->val};
+    const char *why = mcl::host::check(h);
+    if (*why) fail(MCL_EINVAL, std::string(name) + ": " + why);
+    return h;
+}
+
+void host_product(const mcl::host::CSC &a, const mcl::host::CSC &b, int32_t nthreads, mcl_csc *C,
+                  mcl_stats *stats)
+{
+    mcl::host::Out o;
+    mcl::host::spgemm(a, b, mcl::host::threads_for(nthreads), o);
+    C->nrows = a.nrows;
+    C->ncols = b.ncols;
+    C->nnz = o.nnz;
+    C->colptr = o.colptr;
+    C->rowidx = o.rowidx;
+    C->val = o.val;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->flops = o.flops;
+        stats->nnz_product = o.nnz;
+        stats->nnz_kept = o.nnz;
+        stats->t_symbolic_ms = o.t_symbolic_ms;
+        stats->t_numeric_ms = o.t_numeric_ms;
+        stats->t_total_ms = o.t_symbolic_ms + o.t_numeric_ms;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcl_expand_host(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int32_t nthreads, mcl_stats *stats)
+{
+    int rc = guarded([&] {
+        if (!C) fail(MCL_EINVAL, "C is NULL");
+        zero_out(C);
+        const mcl::host::CSC a = host_csc(A, "A"), b = host_csc(B, "B");
+        if (a.ncols != b.nrows) fail(MCL_EINVAL, "A.ncols != B.nrows");
+        host_product(a, b, nthreads, C, stats);
+    });
+    if (rc != MCL_OK && C) zero_out(C);
+    return rc;
+}
+
+void mcl_host_free(mcl_csc *C)
+{
+    if (!C) return;
+    std::free(C->colptr);
+    std::free(C->rowidx);
+    std::free(C->val);
+    zero_out(C);
+}
+
+int mcl_expand_dispatch(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int64_t gpu_min_flops,
+                        int32_t nthreads, const mcl_params *params, const mcl_allocator *alloc,
+                        void *stream, mcl_stats *stats, int32_t *where)
+{
+    mcl_csc dC{};
+    Mem mem{alloc, (hipStream_t)stream};
+    int rc = guarded([&] {
+        if (!C) fail(MCL_EINVAL, "C is NULL");
+        zero_out(C);
+        const mcl::host::CSC a = host_csc(A, "A"), b = host_csc(B, "B");
+        if (a.ncols != b.nrows) fail(MCL_EINVAL, "A.ncols != B.nrows");
+        const auto t0 = std::chrono::steady_clock::now();
+        const int nt = mcl::host::threads_for(nthreads);
+        const int64_t fl = mcl::host::flops(a, b, nt);
+        const int64_t cut = gpu_min_flops > 0 ? gpu_min_flops : (int64_t)MCL_DISPATCH_GPU_MIN_FLOPS;
+        if (where) *where = fl >= cut ? 1 : 0;
+        if (fl < cut) {
+            host_product(a, b, nthreads, C, stats);
+            if (stats)
+                stats->t_total_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            return;
+        }
+        // GPU: upload A and B, expand, download C
+        mcl_csc dA{a.nrows, a.ncols, a.nnz, nullptr, nullptr, nullptr};
+        mcl_csc dB{b.nrows, b.ncols, b.nnz, nullptr, nullptr, nullptr};
+        for (auto pr : {std::make_pair(&dA, A), std::make_pair(&dB, B)}) {
+            mcl_csc &d = *pr.first;
+            d.colptr = mem.ws<int64_t>(d.ncols + 1);
+            d.rowidx = mem.ws<int32_t>(d.nnz);
+            d.val = mem.ws<double>(d.nnz);
+            HIPC(hipMemcpyAsync(d.colptr, pr.second->colptr, sizeof(int64_t) * (d.ncols + 1),
+                                hipMemcpyHostToDevice, mem.st));
+            if (d.nnz > 0) {
+                HIPC(hipMemcpyAsync(d.rowidx, pr.second->rowidx, sizeof(int32_t) * d.nnz,
+                                    hipMemcpyHostToDevice, mem.st));
+                HIPC(hipMemcpyAsync(d.val, pr.second->val, sizeof(double) * d.nnz, hipMemcpyHostToDevice,
+                                    mem.st));
+            }
+        }
+        const int e = mcl_expand(&dA, &dB, &dC, params, alloc, stream, stats);
+        if (e != MCL_OK) fail(e, g_err);
+        // the device C belongs to this call until it is copied out
+        mem.work.push_back(dC.colptr);
+        mem.work.push_back(dC.rowidx);
+        mem.work.push_back(dC.val);
+        mem.wsz.insert(mem.wsz.end(), 3, 0);
+        const int64_t n = dC.ncols, nz = dC.nnz;
+        dC = mcl_csc{};
+        int64_t *hc = (int64_t *)std::malloc(sizeof(int64_t) * (size_t)(n + 1));
+        int32_t *hr = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nz, 1));
+        double *hv = (double *)std::malloc(sizeof(double) * (size_t)std::max<int64_t>(nz, 1));
+        C->colptr = hc;
+        C->rowidx = hr;
+        C->val = hv;
+        if (!hc || !hr || !hv) fail(MCL_ENOMEM, "host out of memory for C");
+        HIPC(hipMemcpyAsync(hc, mem.work[mem.work.size() - 3], sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost,
+                            mem.st));
+        if (nz > 0) {
+            HIPC(hipMemcpyAsync(hr, mem.work[mem.work.size() - 2], sizeof(int32_t) * nz, hipMemcpyDeviceToHost,
+                                mem.st));
+            HIPC(hipMemcpyAsync(hv, mem.work[mem.work.size() - 1], sizeof(double) * nz, hipMemcpyDeviceToHost,
+                                mem.st));
+        }
+        HIPC(hipStreamSynchronize(mem.st));
+        C->nrows = a.nrows;
+        C->ncols = n;
+        C->nnz = nz;
+        if (stats)
+            stats->t_total_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    });
+    if (rc != MCL_OK) {
+        (void)hipStreamSynchronize(mem.st);
+        if (dC.colptr) {  // mcl_expand succeeded but the call failed before taking C
+            mem.release(dC.colptr);
+            mem.release(dC.rowidx);
+            mem.release(dC.val);
+        }
+        if (C) mcl_host_free(C);
+    }
+    mem.free_work();
+    (void)hipStreamSynchronize(mem.st);
     return rc;
 }
 

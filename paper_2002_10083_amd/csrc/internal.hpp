@@ -42,9 +42,9 @@ struct NumericArgs {
     PruneArgs pa;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
-    const int32_t *srow;     // sliced copy of A (column ranges of A.colptr): rows
-    const double *sval;       //   and values
-    uint32_t src_end;         // sliced copy: index of the entry past the last (row -1, value 0)
+    const uint32_t *srec;     // sliced copy of A (column ranges of A.colptr) as packed 12-byte
+                              //   records {row, value low word, value high word}
+    uint32_t src_end;         // sliced copy: index of the record past the last (row -1, value 0)
     const uint8_t *hbm_only;  // columns sized by an exact count: HBM-table kernel only (or null)
     int32_t *part_cnt;        // split sliced kernels: keys appended per column (all zero between launches)
     int64_t *exact_cnt;       // split sliced kernels: exact key count of an overflowed column, -1 = unknown
@@ -67,8 +67,10 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
                           hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,
                        int32_t *ph_bin, int64_t *ph_base, int32_t *counts, hipStream_t st);
-// sliced copy of A: rows and values, each column ordered by row group, + group boundaries
-void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st);
+// sliced copy of A: rows and values, each column ordered by row group, as separate arrays and
+// as packed 12-byte records (same order), + group boundaries
+void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, uint32_t *reco, int32_t *goff,
+                         hipStream_t st);
 // Cohen keys per row are stored with this stride (r rounded up to 4)
 inline int cohen_stride(int r) { return (r + 3) & ~3; }
 // Column records of A for the symbolic pass: RP key minima (RP = padded key

@@ -1421,11 +1421,18 @@ __device__ __forceinline__ int row_group(int32_t r) { return (int)(row_hash(r) >
 __device__ __forceinline__ uint32_t hash_bucket(uint32_t h, int logNB) { return (h << 6) >> (32 - logNB); }
 __device__ __forceinline__ uint32_t sub_bucket(int32_t r, int logNB) { return hash_bucket(row_hash(r), logNB); }
 
+// A record of the packed sliced copy: row, then the value's low and high
+// words.  12 bytes with 4-byte alignment, so one dwordx3 load per entry and
+// a run of a column is one contiguous byte range (fewer partially used
+// cache lines than a row range plus a value range).
+typedef uint32_t rec3 __attribute__((ext_vector_type(3), aligned(4)));
+
 // One wave per column: group sizes (LDS counters), boundaries, then a
 // scatter by LDS cursors.  The order of the entries inside a group is not
 // specified (every consumer treats a run as a set of distinct rows).
 __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restrict__ rowo,
-                                                      double *__restrict__ valo, int32_t *__restrict__ goff)
+                                                      double *__restrict__ valo, uint32_t *__restrict__ reco,
+                                                      int32_t *__restrict__ goff)
 {
     __shared__ int32_t ctr[4][NG];
     const int w = threadIdx.x / WAVE;
@@ -1448,16 +1455,21 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
     for (int e = lane(); e < len; e += WAVE) {
         const int32_t r = A.rowidx[p0 + e];
         const int64_t d = p0 + atomicAdd(&c[row_group(r)], 1);
+        const double v = A.val[p0 + e];
         rowo[d] = r;
-        valo[d] = A.val[p0 + e];
+        valo[d] = v;
+        const uint64_t vb = (uint64_t)__double_as_longlong(v);
+        *(__attribute__((address_space(1))) rec3 *)(reco + d * 3) = rec3{(uint32_t)r, (uint32_t)vb,
+                                                                         (uint32_t)(vb >> 32)};
     }
 }
 
-void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, int32_t *goff, hipStream_t st)
+void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, uint32_t *reco, int32_t *goff,
+                         hipStream_t st)
 {
     if (A.ncols <= 0) return;
     hipLaunchKernelGGL(k_slice_layout, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A, rowo, valo,
-                       goff);
+                       reco, goff);
 }
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
@@ -1577,8 +1589,9 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 const int F = (c0 + i) * WAVE;
                 // past the run ends: the sentinel entry (row -1, value 0)
                 const uint32_t ad = (F + lane() < total) ? bu[i] + (uint32_t)(F + lane()) : a.src_end;
-                G.rr[i] = ldg(a.srow + (uint64_t)ad);
-                if (MODE != MODE_COUNT) G.vv[i] = ldg(a.sval + (uint64_t)ad);
+                const rec3 x = ldg((const rec3 *)(a.srec + (uint64_t)ad * 3));
+                G.rr[i] = (int32_t)x.x;
+                if (MODE != MODE_COUNT) G.vv[i] = __longlong_as_double((int64_t)(((uint64_t)x.z << 32) | x.y));
             }
         };
         auto fold_dense = [&](Grp &G) {

@@ -118,12 +118,24 @@ _lib.mcl_mlp_init.argtypes = [_P, ctypes.c_uint64, _P]
 _lib.mcl_mlp_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float,
                                     ctypes.POINTER(ctypes.c_float), _P, _P]
 
+_lib.mcl_expand_host.argtypes = [ctypes.POINTER(_CSC), ctypes.POINTER(_CSC), ctypes.POINTER(_CSC),
+                                 ctypes.c_int32, ctypes.POINTER(Stats)]
+_lib.mcl_host_free.argtypes = [ctypes.POINTER(_CSC)]
+_lib.mcl_expand_dispatch.argtypes = [ctypes.POINTER(_CSC), ctypes.POINTER(_CSC), ctypes.POINTER(_CSC),
+                                     ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Params),
+                                     ctypes.POINTER(_Allocator), _P, ctypes.POINTER(Stats),
+                                     ctypes.POINTER(ctypes.c_int32)]
+
 #: every symbol include/mcl.h declares
 EXPORTS = ("mcl_default_params", "mcl_normalize", "mcl_expand", "mcl_prune", "mcl_inflate",
            "mcl_iterate", "mcl_merge_partials", "mcl_components", "mcl_components_noalloc",
            "mcl_symbolic", "mcl_estimate",
            "mcl_mlp_packed_bytes", "mcl_mlp_forward", "mcl_mlp_state_floats", "mcl_mlp_init",
-           "mcl_mlp_train_step", "mcl_last_error")
+           "mcl_mlp_train_step", "mcl_last_error", "mcl_expand_host", "mcl_host_free",
+           "mcl_expand_dispatch")
+
+#: default flops threshold of mcl_expand_dispatch (include/mcl.h)
+DISPATCH_GPU_MIN_FLOPS = 16_000_000
 
 
 def _check(rc):
@@ -392,6 +404,68 @@ def estimate(A: DeviceCSC, B: DeviceCSC, params: Optional[Params] = None, featur
                              feat.data_ptr() if features else None, ctypes.byref(al.struct),
                              _stream()))
     return (est, feat.view(B.ncols, 12)) if features else est
+
+
+# ---- host matrices: CPU hash SpGEMM and the CPU/GPU dispatch
+def _host_c(m):
+    """C descriptor of a host CSC (numpy arrays, kept alive by the caller)."""
+    cp = np.ascontiguousarray(m.colptr, np.int64)
+    ri = np.ascontiguousarray(m.rowidx, np.int32)
+    va = np.ascontiguousarray(m.val, np.float64)
+    keep = (cp, ri, va)
+    c = _CSC(int(m.nrows), int(m.ncols), int(cp[-1]) if cp.size else 0, cp.ctypes.data,
+             ri.ctypes.data if ri.size else 0, va.ctypes.data if va.size else 0)
+    return c, keep
+
+
+def _take_host(c: _CSC):
+    """Copy a library-allocated host matrix into numpy arrays and free it."""
+    from mclgen import CSC
+    n, nz = int(c.ncols), int(c.nnz)
+    try:
+        cp = np.ctypeslib.as_array(ctypes.cast(c.colptr, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        if nz:
+            ri = np.ctypeslib.as_array(ctypes.cast(c.rowidx, ctypes.POINTER(ctypes.c_int32)), (nz,)).copy()
+            va = np.ctypeslib.as_array(ctypes.cast(c.val, ctypes.POINTER(ctypes.c_double)), (nz,)).copy()
+        else:
+            ri, va = np.zeros(0, np.int32), np.zeros(0, np.float64)
+    finally:
+        _lib.mcl_host_free(ctypes.byref(c))
+    return CSC(int(c.nrows), n, cp, ri, va)
+
+
+def expand_host(A, B, nthreads: int = 0):
+    """mcl_expand_host: C = A B on the host's cores (multithreaded hash
+    SpGEMM) for host CSC matrices.  Returns (C as a host CSC, stats dict)."""
+    a, ka = _host_c(A)
+    b, kb = _host_c(B)
+    out = _CSC()
+    st = Stats()
+    _check(_lib.mcl_expand_host(ctypes.byref(a), ctypes.byref(b), ctypes.byref(out), int(nthreads),
+                                ctypes.byref(st)))
+    del ka, kb
+    return _take_host(out), st.as_dict()
+
+
+def expand_dispatch(A, B, gpu_min_flops: int = 0, nthreads: int = 0, params: Optional[Params] = None,
+                    **kw):
+    """mcl_expand_dispatch: host matrices in and out; the product runs on the
+    CPU when its flops are below gpu_min_flops (0 = the library's measured
+    default), else on the GPU.  Returns (C, stats dict, "cpu" | "gpu")."""
+    p = _params(params, kw)
+    al = _allocator()
+    a, ka = _host_c(A)
+    b, kb = _host_c(B)
+    out = _CSC()
+    st = Stats()
+    where = ctypes.c_int32(-1)
+    _check(_lib.mcl_expand_dispatch(ctypes.byref(a), ctypes.byref(b), ctypes.byref(out),
+                                    int(gpu_min_flops), int(nthreads), ctypes.byref(p),
+                                    ctypes.byref(al.struct),
+                                    _stream() if torch.cuda.is_available() else None,
+                                    ctypes.byref(st), ctypes.byref(where)))
+    del ka, kb
+    return _take_host(out), st.as_dict(), ("gpu" if where.value == 1 else "cpu")
 
 
 # ---- learned estimator
