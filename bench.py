@@ -387,26 +387,38 @@ def bench_batched(args, seed=5):
                   "per_call_ms": [round(s_["ms"], 2) for s_ in info["steps"]]})
 
 
-def bench_mlp(args, train_seeds=(2001, 2002, 2003), n_train=250_000):
-    """Learned table sizing: train the 12-64-64-1 MLP on other seeds with the
-    library's kernels, then compare the fused iteration on the 1M-vertex graph
-    with Cohen sizing (same output, different overflow and time)."""
+def bench_mlp(args, cfg1_seeds=tuple(range(2001, 2009)), cfg3_seeds=(2101, 2102), heldout_seed=2009,
+              scales=(0.7, 0.85, 1.0, 1.2, 1.45, 1.75), reps=3):
+    """Learned table sizing.  Training rows are logged from the method's own
+    runs on graphs of the benchmark's shapes with other seeds (1M-vertex
+    planted graphs, 4 iterations each, and 20,000-component graphs, 3
+    iterations each); the MLP is trained with the library's kernels; its
+    sizing margin is the 0.75-quantile of its log residual on a held-out
+    1M-vertex graph (Cohen's margin is the tuned one).  Then the fused
+    iteration on the benchmark graph (seed 1001) runs with each estimator the
+    same number of times, plus the same sweep of margins for both."""
     import numpy as np
     import torch
-    from mclgen import config1_graph
+    from mclgen import config1_graph, config3_graph
     from paper_2002_10083_amd import learned, mcl, tuning
     policy, scale, keys = tuning.load_policy("iterate")
-    base = dict(bin_policy=policy, est_scale=scale, cohen_keys=keys)
+    base = dict(bin_policy=policy, cohen_keys=keys)
+    cohen_kw = dict(estimator=mcl.EST_COHEN)
     Xs, ys = [], []
     t = time.time()
-    for sd in train_seeds:
-        Wt = config1_graph(seed=sd, n=n_train, n_clusters=n_train // 20)
-        At = mcl.DeviceCSC.from_host(Wt)
+    shapes = [("1M-vertex planted", sd, 4) for sd in cfg1_seeds] + [("20,000 components", sd, 3) for sd in cfg3_seeds]
+    for kind, sd, its in shapes:
+        W = config1_graph(seed=sd) if kind.startswith("1M") else config3_graph(seed=sd)
+        At = mcl.DeviceCSC.from_host(W)
+        del W
         mcl.normalize_(At)
-        X, y = learned.collect(At, iterations=4, params=mcl.default_params(**base))
+        X, y = learned.collect(At, iterations=its, params=mcl.default_params(**base, est_scale=scale))
         Xs.append(X)
         ys.append(y)
+        del At
+        log("collected %s seed %d: %d rows (%.1f s)" % (kind, sd, X.shape[0], time.time() - t))
     X, y = torch.cat(Xs), torch.cat(ys)
+    del Xs, ys
     t_collect = time.time() - t
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -414,36 +426,126 @@ def bench_mlp(args, train_seeds=(2001, 2002, 2003), n_train=250_000):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
     rows_per_s = X.shape[0] * 6 / t_train
+    n_rows = int(X.shape[0])
+    del X, y
+    mlp_kw = dict(estimator=mcl.EST_MLP, mlp_weights=packed)
+    # sizing margins from held-out residuals (iteration 0, the benchmark's)
+    H = mcl.DeviceCSC.from_host(config1_graph(seed=heldout_seed))
+    mcl.normalize_(H)
+    hp = mcl.default_params(**base, est_scale=scale)
+    q_mlp = learned.residual_quantiles(H, dict(mlp_kw), iterations=1, params=hp)
+    q_cohen = learned.residual_quantiles(H, dict(cohen_kw, cohen_keys=keys), iterations=1, params=hp)
+    del H
+    mlp_scale = learned.scale_for_quantile(q_mlp, 0.75)
+    log("held-out residual quantiles: mlp %s cohen %s -> mlp est_scale %.3f" % (q_mlp, q_cohen, mlp_scale))
     W = config1_graph(n=args.n, n_clusters=max(1, args.n // 20))
     A = mcl.DeviceCSC.from_host(W)
     mcl.normalize_(A)
-    runs = {}
-    # Cohen runs with its tuned margin; the MLP margin is picked the same way
-    # (by step time) from a short list
-    trials = [("cohen", dict(estimator=mcl.EST_COHEN))]
-    trials += [("mlp", dict(estimator=mcl.EST_MLP, mlp_weights=packed, est_scale=sc)) for sc in (0.8, 1.0, 1.25)]
-    for name, kw in trials:
-        best = runs.get(name)
-        for _ in range(3):
-            G, ch, st = mcl.iterate(A, mcl.default_params(**dict(base, **kw)))
-            st["est_scale"] = kw.get("est_scale", scale)
-            if best is None or st["t_total_ms"] < best[1]["t_total_ms"]:
-                best = (G, st)
-        runs[name] = best
-    same = (torch.equal(runs["cohen"][0].rowidx, runs["mlp"][0].rowidx)
-            and torch.equal(runs["cohen"][0].val, runs["mlp"][0].val))
+    pick = ("t_total_ms", "t_symbolic_ms", "t_estimate_ms", "t_numeric_ms", "t_fallback_ms", "n_overflow",
+            "n_global")
+
+    def run(kw, sc, n):
+        best, outs = None, None
+        for _ in range(n):
+            G, ch, st = mcl.iterate(A, mcl.default_params(**dict(base, **kw), est_scale=sc))
+            if best is None or st["t_total_ms"] < best["t_total_ms"]:
+                best = st
+            outs = G
+        return outs, dict({k: best[k] for k in pick}, est_scale=round(sc, 4))
+
+    Gc, sc_ = run(cohen_kw, scale, reps)
+    Gm, sm = run(mlp_kw, mlp_scale, reps)
+    same = torch.equal(Gc.rowidx, Gm.rowidx) and torch.equal(Gc.val, Gm.val) and torch.equal(Gc.colptr, Gm.colptr)
+    del Gc, Gm
+    sweep = {"cohen": [], "mlp": []}
+    for name, kw in (("cohen", cohen_kw), ("mlp", mlp_kw)):
+        for sc in scales:
+            _, st = run(kw, sc, 2)
+            sweep[name].append(st)
+    best_c = min(sweep["cohen"], key=lambda d: d["t_total_ms"])
+    best_m = min(sweep["mlp"], key=lambda d: d["t_total_ms"])
     acc = learned.evaluate(packed, A)
-    sc, sm = runs["cohen"][1], runs["mlp"][1]
-    pick = ("t_total_ms", "t_numeric_ms", "t_fallback_ms", "n_overflow", "n_global", "est_scale")
     return _line("fused MCL iteration at n=1M: speedup of learned (MLP) table sizing over Cohen",
-                 round(sc["t_total_ms"] / sm["t_total_ms"], 4), "x", sm["t_total_ms"], True,
-                 "one fused MCL iteration on the 1M-vertex planted graph (seed 1001); MLP trained on "
-                 "seeds %s at n=%d" % (list(train_seeds), n_train),
-                 {"cohen": {k: sc[k] for k in pick}, "mlp": {k: sm[k] for k in pick},
-                  "bit_identical": bool(same), "train_rows": int(X.shape[0]),
-                  "train_rows_per_s": round(rows_per_s, 1), "collect_s": round(t_collect, 1),
-                  "train_s": round(t_train, 2), "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)],
+                 round(sc_["t_total_ms"] / sm["t_total_ms"], 4), "x", sm["t_total_ms"], True,
+                 "one fused MCL iteration on the 1M-vertex planted graph (seed 1001); MLP trained on %d "
+                 "rows from 1M-vertex planted graphs (seeds %d-%d, 4 iterations) and 20,000-component "
+                 "graphs (seeds %s, 3 iterations); margin from held-out seed %d"
+                 % (n_rows, cfg1_seeds[0], cfg1_seeds[-1], list(cfg3_seeds), heldout_seed),
+                 {"cohen": sc_, "mlp": sm, "bit_identical": bool(same), "runs_each": reps,
+                  "margin_rule": "est_scale = exp(Q0.75 of held-out log residual) / 1.3",
+                  "heldout_residual_quantiles": {"mlp": q_mlp, "cohen": q_cohen},
+                  "sweep": sweep,
+                  "best_of_sweep_speedup": round(best_c["t_total_ms"] / best_m["t_total_ms"], 4),
+                  "train_rows": n_rows, "train_rows_per_s": round(rows_per_s, 1),
+                  "collect_s": round(t_collect, 1), "train_s": round(t_train, 2),
+                  "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)],
                   "log_error": acc}, dtype="bf16/f32 MLP, f64 expansion")
+
+
+def bench_dispatch(args, sizes=(100, 200, 300, 500, 700, 1000, 1500, 2000, 4000, 16000, 64000), reps=5):
+    """The CPU/GPU dispatch by flops (host matrices in and out): the CPU hash
+    SpGEMM on every host thread against the GPU expansion including both
+    copies, on planted graphs of growing size.  The flops where the GPU leg
+    becomes faster is the dispatch threshold.  Also the host SpGEMM's rate on
+    the 1M-vertex benchmark graph, next to the oracle's."""
+    import numpy as np
+    import torch
+    from mclgen import config1_graph
+    from paper_2002_10083_amd import mcl
+    rows = []
+    for i, n in enumerate(sizes):
+        A = mcl.DeviceCSC.from_host(config1_graph(seed=4000 + i, n=n, n_clusters=max(1, n // 20)))
+        mcl.normalize_(A)
+        H = A.to_host()
+        t = {}
+        outs = {}
+        for leg, cut in (("cpu", 1 << 62), ("gpu", 1)):
+            best = None
+            for _ in range(reps):
+                C, st, where = mcl.expand_dispatch(H, H, gpu_min_flops=cut)
+                assert where == leg
+                best = st["t_total_ms"] if best is None else min(best, st["t_total_ms"])
+            t[leg] = best
+            outs[leg] = C
+            fl = st["flops"]
+        same = (np.array_equal(outs["cpu"].rowidx, outs["gpu"].rowidx)
+                and np.array_equal(outs["cpu"].val.view(np.uint64), outs["gpu"].val.view(np.uint64)))
+        rows.append({"n": n, "flops": int(fl), "cpu_ms": round(t["cpu"], 3), "gpu_ms": round(t["gpu"], 3),
+                     "bit_identical": bool(same)})
+        log("dispatch n=%d flops=%.3g cpu %.2f ms gpu %.2f ms same=%s" % (n, fl, t["cpu"], t["gpu"], same))
+    # crossover: between the largest product the CPU leg still wins and the
+    # next larger one (geometric mean of their flops)
+    by = sorted(rows, key=lambda r: r["flops"])
+    last_cpu = max((i for i, r in enumerate(by) if r["cpu_ms"] < r["gpu_ms"]), default=None)
+    if last_cpu is None:
+        cross = None  # the GPU leg wins at every size measured
+    elif last_cpu + 1 < len(by):
+        cross = float(np.sqrt(by[last_cpu]["flops"] * by[last_cpu + 1]["flops"]))
+    else:
+        cross = float(by[-1]["flops"])
+    W = config1_graph(n=args.n, n_clusters=max(1, args.n // 20))
+    A = mcl.DeviceCSC.from_host(W)
+    mcl.normalize_(A)
+    H = A.to_host()
+    del W
+    t = time.perf_counter()
+    C, st = mcl.expand_host(H, H)
+    host_s = time.perf_counter() - t
+    host_rate = st["flops"] / (st["t_total_ms"] * 1e6)
+    G, gst = mcl.expand(A, A)
+    same = (np.array_equal(C.colptr, G.colptr.cpu().numpy()) and np.array_equal(C.rowidx, G.rowidx.cpu().numpy())
+            and np.array_equal(C.val.view(np.uint64), G.val.cpu().numpy().view(np.uint64)))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return _line("host hash SpGEMM GFLOP/s at n=1M and the CPU/GPU dispatch crossover", round(host_rate, 3),
+                 "GFLOP/s", st["t_total_ms"], True,
+                 "expansion A*A of the 1M-vertex planted graph (seed 1001) on the host's threads; dispatch "
+                 "sweep on planted graphs of %d..%d vertices" % (sizes[0], sizes[-1]),
+                 {"host_threads": threads, "cpu_model": cpu_model(), "host_wall_s": round(host_s, 2),
+
+                  "gpu_expand_ms": round(gst["t_total_ms"], 3),
+                  "gpu_GFLOPs": round(gst["flops"] / (gst["t_total_ms"] * 1e6), 2),
+                  "bit_identical_vs_gpu": bool(same), "sweep": rows,
+                  "crossover_flops": None if cross is None else round(cross)})
 
 
 def main():
@@ -463,7 +565,7 @@ def main():
                     help="merge workload: vertices of the whole graph (8 x 8 grid)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="iterate", choices=["iterate", "merge", "batched", "mlp"],
+    ap.add_argument("--workload", default="iterate", choices=["iterate", "merge", "batched", "mlp", "dispatch"],
                     help="iterate: one fused iteration at n=1M (default); merge: 8 SUMMA-stage "
                          "partials merged by Alg. 2 vs one flat merge; batched: MCL to convergence "
                          "over 20,000 components, batched vs per component; mlp: learned vs Cohen "
@@ -476,7 +578,8 @@ def main():
     if args.workload != "iterate":
         import torch
         torch.cuda.set_device(0)
-        out = {"merge": bench_merge, "batched": bench_batched, "mlp": bench_mlp}[args.workload](args)
+        out = {"merge": bench_merge, "batched": bench_batched, "mlp": bench_mlp,
+               "dispatch": bench_dispatch}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -56,6 +56,9 @@ extern "C" {
 #define MCL_ENOMEM (-2)   /* the allocator returned NULL */
 #define MCL_EHIP (-3)     /* HIP runtime error (text in mcl_last_error) */
 
+/* bin_policy flag: one persistent accumulation launch for LDS bins 0-6 */
+#define MCL_POLICY_PERSIST (1 << 28)
+
 /* Output-size estimator used to size the per-column hash tables. */
 #define MCL_EST_BOUND 0   /* exact-safe bound min(flops_j, row span_j) */
 #define MCL_EST_COHEN 1   /* Cohen's exponential-key estimate (Section 5) */
@@ -88,7 +91,11 @@ typedef struct {
     double est_scale;        /* multiplies every estimate (test knob; 1.0) */
     const void *mlp_weights; /* device pointer to the packed BF16 MLP (MCL_EST_MLP) */
     int32_t validate;        /* nonzero: check the CSC invariants of every input */
-    int32_t bin_policy;      /* launch shape per table bin, 4 bits per bin (0 = default) */
+    int32_t bin_policy;      /* launch shape per table bin, 4 bits per bin (0 = default); bit 28
+                                (MCL_POLICY_PERSIST): accumulate the columns of all LDS bins
+                                (0-6) in one persistent launch whose waves take (column, part)
+                                work items from a queue, heaviest bins first, then finish each
+                                bin (sort, epilogue) -- same results */
     float *est_out;          /* optional device float[ncols]: the estimate used per column */
     int64_t *nnz_out;        /* optional device int64[ncols]: exact nnz of each product column */
     int64_t phase_bytes;     /* mcl_iterate: bound on the product's temporary storage; when the
@@ -121,7 +128,10 @@ typedef struct {
     /* bins whose columns are split over several workgroups (an accumulation
        kernel, then a kernel that sorts each column and runs the epilogue):
        time of the accumulation kernel alone (0 for other bins), and the
-       unpruned product entries of every bin's columns */
+       unpruned product entries of every bin's columns.  With the persistent
+       accumulation (bin_policy bit 28, MCL_POLICY_PERSIST) bins 0-6 share
+       one accumulation launch: bin_ms[0] then holds the time of all of
+       bins 0-6, bin_part_ms[0] that of the shared accumulation launch. */
     double bin_part_ms[8];
     int64_t bin_prod[8];
     int64_t n_dense;          /* columns accumulated in a dense array over their row span */
@@ -257,17 +267,20 @@ int mcl_mlp_train_step(float *state, void *packed, const float *feat, const floa
 
 /* Multithreaded CPU hash SpGEMM, the paper's host expansion (Section 6
  * "Faster SpGEMM on CPU"): C = A*B, unpruned, with HOST matrices.  Every
- * worker thread keeps one hash table for its lifetime (sized for the largest
- * column it has met); a symbolic pass counts each output column, a numeric
- * pass accumulates and sorts it by row.  Products are accumulated in the
+ * worker thread keeps one hash table for its lifetime (grown to the largest
+ * column it has met); a column is accumulated in it, sorted by row and
+ * appended to the worker's buffer, and the buffers are copied into place
+ * once every column is counted (instead of a separate symbolic pass).
+ * Products are accumulated in the
  * library's order (ascending k, product rounded before the addition), so C
- * is bit-identical to mcl_expand's.  nthreads <= 0 uses every hardware
+ * is bit-identical to mcl_expand's.  nthreads <= 0 uses OMP_NUM_THREADS
+ * threads when that variable holds a positive count, else every hardware
  * thread.  A, B: host arrays, read only; every call checks their structure
  * (colptr[0] == 0, non-decreasing colptr, colptr[ncols] == nnz, rows in
  * range) -- MCL_EINVAL otherwise, or for A.ncols != B.nrows.  C receives
  * malloc'd host arrays that the caller releases with mcl_host_free.  stats
- * (nullable): flops, nnz_product = nnz_kept = nnz(C), t_symbolic_ms,
- * t_numeric_ms, t_total_ms; the other fields are zero.  MCL_ENOMEM when host
+ * (nullable): flops, nnz_product = nnz_kept = nnz(C), t_numeric_ms =
+ * t_total_ms (the whole product); the other fields are zero.  MCL_ENOMEM when host
  * memory runs out (nothing is leaked, C is zeroed). */
 int mcl_expand_host(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int32_t nthreads, mcl_stats *stats);
 
@@ -282,12 +295,13 @@ void mcl_host_free(mcl_csc *C);
  * device (arrays from `alloc` on `stream`), multiplied by mcl_expand with
  * `params`, and C is copied back.  gpu_min_flops <= 0 selects
  * MCL_DISPATCH_GPU_MIN_FLOPS, the crossover measured on one MI355X with its
- * host (GPU time including both copies vs 16 host threads).  Either way C
+ * host (GPU time including both copies vs 16 host threads: 3.1e6 flops on
+ * planted graphs).  Either way C
  * holds malloc'd host arrays (release with mcl_host_free) and is
  * bit-identical.  where (nullable) receives 0 (CPU) or 1 (GPU); stats as in
  * mcl_expand_host or mcl_expand, with t_total_ms covering the whole call
  * (copies included).  Errors as in mcl_expand_host and mcl_expand. */
-#define MCL_DISPATCH_GPU_MIN_FLOPS 16000000
+#define MCL_DISPATCH_GPU_MIN_FLOPS 3000000
 int mcl_expand_dispatch(const mcl_csc *A, const mcl_csc *B, mcl_csc *C, int64_t gpu_min_flops,
                         int32_t nthreads, const mcl_params *params, const mcl_allocator *alloc,
                         void *stream, mcl_stats *stats, int32_t *where);

@@ -14,6 +14,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--key", default="iterate")
     ap.add_argument("--copy-to", default=None, help="also write the table to this file")
+    ap.add_argument("--persist-only", action="store_true",
+                    help="keep the stored launch shapes of --key and only decide whether bins 0-6 "
+                         "accumulate in one persistent launch")
     ap.add_argument("--workload", default="iterate", choices=["iterate", "batched"],
                     help="iterate: one fused iteration of the 1M-vertex graph; batched: the first three "
                          "iterations of the 20,000-component graph, all components per call")
@@ -50,6 +53,18 @@ def main():
         return tot
 
     t = time.time()
+    if args.persist_only:
+        policy, scale, keys = tuning.load_policy(args.key)
+        with open(tuning.TUNED) as f:
+            import json
+            rep = json.load(f).get(args.key, {})
+        rep.pop("bin_policy", None)
+        rep.pop("est_scale", None)
+        rep.pop("cohen_keys", None)
+        policy, rep["persist"] = tuning.decide_persist(run, policy, scale, keys)
+        tuning.save_policy(args.key, policy, scale, keys, rep)
+        print("tuned", hex(policy), scale, keys, rep["persist"], flush=True)
+        return
     if args.workload == "batched":
         # three iterations per trial: one measurement each, only the launch
         # shapes that were within 30 % of the best on the 1M-vertex graph,
@@ -59,6 +74,7 @@ def main():
                                                scales=(sc0,), keys=(k0,))
     else:
         policy, scale, keys, rep = tuning.tune(run)
+    policy, rep["persist"] = tuning.decide_persist(run, policy, scale, keys)
     rep["tune_s"] = round(time.time() - t, 1)
     rep["gpu"] = torch.cuda.get_device_name(0)
     tuning.save_policy(args.key, policy, scale, keys, rep)

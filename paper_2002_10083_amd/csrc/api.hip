@@ -274,7 +274,36 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
     std::vector<hipEvent_t> ev;
     std::vector<int> evbin;
     std::vector<hipEvent_t> evmid;  // per timed bin: between the kernels of a split launch (or null)
-    for (int b = 0; b < 8; ++b) {
+    // persistent accumulation of the LDS bins (policy flag): one launch for
+    // bins 0-6, timed as bin 0 (accumulation in bin_part_ms[0])
+    const bool persist = (policy & mcl::POLICY_PERSIST) && mode != mcl::MODE_COUNT && a.goff && a.part_cnt &&
+                         mcl::persist_fits(counts);
+    if (persist) {
+        int32_t nlds = 0;
+        for (int b = 0; b < mcl::NUM_LDS_BINS; ++b) nlds += counts[b];
+        if (nlds > 0) {
+            hipEvent_t e0 = nullptr, e1 = nullptr, em = nullptr;
+            if (timed) {
+                HIPC(hipEventCreate(&e0));
+                HIPC(hipEventCreate(&e1));
+                HIPC(hipEventCreate(&em));
+                HIPC(hipEventRecord(e0, mem.st));
+            }
+            uint32_t *next = mem.ws<uint32_t>(1);
+            mcl::launch_numeric_persist(mode, a, lists, counts, dense_bin, next, mem.st, em);
+            HIPC(hipGetLastError());
+            if (timed) {
+                HIPC(hipEventRecord(e1, mem.st));
+                ev.push_back(e0);
+                ev.push_back(e1);
+                evbin.push_back(0);
+                evmid.push_back(em);
+            }
+            for (int b = 0; b < mcl::NUM_LDS_BINS; ++b) eo.bin_cols[b] += counts[b];
+        }
+        off = nlds;
+    }
+    for (int b = persist ? mcl::NUM_LDS_BINS : 0; b < 8; ++b) {
         const int32_t c = counts[b];
         if (c > 0) {
             a.cols = lists + off;

@@ -32,8 +32,8 @@ struct Out {
 // string when the matrix is well formed, else what is wrong.
 const char *check(const CSC &m);
 
-// Number of worker threads: nthreads > 0 as given, else the host's hardware
-// concurrency.
+// Number of worker threads: nthreads > 0 as given, else OMP_NUM_THREADS when
+// it is set to a positive count, else the host's hardware concurrency.
 int threads_for(int nthreads);
 
 // flops = sum_j sum_{k in B_*j} nnz(A_*k) on `threads` workers.

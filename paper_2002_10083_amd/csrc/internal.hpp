@@ -53,6 +53,17 @@ struct NumericArgs {
 
 // ---- spgemm.hip
 constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced source layout
+// bin_policy bit: accumulate LDS bins 0-6 in one persistent launch
+constexpr uint32_t POLICY_PERSIST = 1u << 28;
+// Work schedule of the persistent accumulation: entry e covers the columns
+// of bin `bin[e]` (at `off[e]` in the bin lists), 2^parts[e] items per
+// column; items [first[e], first[e + 1]) belong to entry e (fewer than 2^31
+// items in all).
+struct PersistSched {
+    int32_t n;
+    int32_t bin[7], parts[7], off[7];
+    int64_t first[8];
+};
 // the sliced kernels index the sliced copy of A (and its sentinel) with 32-bit entry indices
 constexpr int64_t SLICE_MAX_NNZ = (int64_t{1} << 32) - 2;
 constexpr int NUM_LDS_BINS = 7;                      // tables of 128 .. 8192 slots
@@ -63,6 +74,13 @@ bool lds_variant_split(int bin, int variant);        // split sliced tables (nee
 // phase [c0, c1) of a phased product: bins (-1 outside), phase-relative temp offsets, bin counts
 // largest columns: multi-pass LDS accumulation + sort/epilogue in HBM scratch
 size_t mpass_slab_bytes();
+// whether the LDS bins' columns fit one persistent accumulation launch
+bool persist_fits(const int32_t counts[8]);
+// the persistent accumulation of bins 0-6 (dense launches first, finishing
+// launches after; mid, nullable, is recorded after the accumulation);
+// `next` is a device counter (zeroed here)
+void launch_numeric_persist(NumericMode mode, const NumericArgs &a, const int32_t *lists, const int32_t counts[8],
+                            const int64_t *dense_bin, uint32_t *next, hipStream_t st, hipEvent_t mid);
 void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
                           hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,

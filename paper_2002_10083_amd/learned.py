@@ -40,9 +40,42 @@ def collect(A: "mcl.DeviceCSC", iterations: int = 4, params=None, log=None):
     return torch.cat(feats), torch.cat(targs)
 
 
+def residual_quantiles(A: "mcl.DeviceCSC", est_kw: dict, iterations: int = 2, params=None,
+                       qs=(0.5, 0.75, 0.9, 0.95, 0.99), min_est: float = 384.0):
+    """Quantiles of log(nnz) - log(estimate) over the columns an estimator
+    sizes (estimate above `min_est`; smaller columns are planned by their
+    exact-safe bound), pooled over the first `iterations` MCL iterations of A."""
+    res = []
+    for it in range(iterations):
+        nnz = torch.empty(A.ncols, dtype=torch.int64, device="cuda")
+        An, change, _ = mcl.iterate(A, params, nnz_out=nnz, iteration=it)
+        est = mcl.estimate(A, A, iteration=it, **est_kw)
+        m = est > min_est
+        res.append((torch.log(nnz.double().clamp(min=1)) - torch.log(est.double().clamp(min=1)))[m])
+        A = An
+        if change < 1e-9:
+            break
+    r = torch.cat(res).float()
+    if r.numel() > (1 << 24):  # torch.quantile's input limit
+        r = r[torch.randperm(r.numel(), device=r.device)[:1 << 24]]
+    q = torch.quantile(r, torch.tensor(list(qs), device=r.device))
+    return {float(k): float(v) for k, v in zip(qs, q)}
+
+
+#: the planner sizes a column for 1.3 * est_scale * estimate keys
+PLAN_MARGIN = 1.3
+
+
+def scale_for_quantile(quantiles: dict, q: float = 0.75) -> float:
+    """est_scale that sizes every column for exp(Q_q) times its estimate,
+    Q_q the q-quantile of the log residual on held-out graphs."""
+    return float(np.exp(quantiles[q]) / PLAN_MARGIN)
+
+
 def train(X: torch.Tensor, y: torch.Tensor, epochs: int = 4, batch: int = 65536, lr: float = 2e-3,
-          seed: int = 0, log=None):
-    """Train from scratch with the GPU kernels; returns (state, packed, losses)."""
+          seed: int = 0, log=None, decay: float = 0.5):
+    """Train from scratch with the GPU kernels (learning rate lr * decay**epoch);
+    returns (state, packed, losses)."""
     state, packed = mcl.mlp_init(seed)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -56,7 +89,7 @@ def train(X: torch.Tensor, y: torch.Tensor, epochs: int = 4, batch: int = 65536,
             idx = perm[s:s + batch]
             if idx.numel() < 256:
                 continue
-            lr_t = lr * (0.5 ** ep)
+            lr_t = lr * (decay ** ep)
             el.append(mcl.mlp_train_step(state, packed, X[idx].contiguous(), y[idx].contiguous(),
                                          lr=lr_t))
         losses.append(float(np.mean(el)))

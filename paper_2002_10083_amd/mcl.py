@@ -135,7 +135,7 @@ EXPORTS = ("mcl_default_params", "mcl_normalize", "mcl_expand", "mcl_prune", "mc
            "mcl_expand_dispatch")
 
 #: default flops threshold of mcl_expand_dispatch (include/mcl.h)
-DISPATCH_GPU_MIN_FLOPS = 16_000_000
+DISPATCH_GPU_MIN_FLOPS = 3_000_000
 
 
 def _check(rc):

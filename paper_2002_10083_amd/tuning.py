@@ -31,6 +31,7 @@ def unpack(policy: int):
     return [(policy >> (4 * b)) & 15 for b in range(len(VARIANTS))]
 
 
+
 def load_policy(key: str, default=(0, 1.0, 5)):
     """(bin_policy, est_scale, cohen_keys) stored for `key`, else `default`."""
     try:
@@ -58,6 +59,32 @@ def save_policy(key: str, policy: int, scale: float, keys: int, info: dict, path
     d[key] = dict(bin_policy=hex(policy), est_scale=scale, cohen_keys=keys, **info)
     with open(path, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
+
+
+#: bin_policy flag: accumulate LDS bins 0-6 in one persistent launch
+PERSIST = 1 << 28
+
+
+def decide_persist(run, policy: int, scale: float, keys: int, reps: int = 2, log=print):
+    """Times the stored launch shapes with and without the persistent
+    accumulation (whole-step wall time, best of `reps`); returns the faster
+    policy and both times."""
+    import torch
+    ms = {}
+    for on in (False, True):
+        pol = (policy | PERSIST) if on else (policy & ~PERSIST)
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            run(pol, scale, keys)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) * 1e3
+            best = dt if best is None else min(best, dt)
+        ms[on] = best
+        log("persistent accumulation %s: %.1f ms" % ("on" if on else "off", best))
+    pol = (policy | PERSIST) if ms[True] < ms[False] else (policy & ~PERSIST)
+    return pol, {"off_ms": round(ms[False], 3), "on_ms": round(ms[True], 3)}
 
 
 def candidates_from(key: str, slack: float = 1.3):

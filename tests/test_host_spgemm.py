@@ -87,7 +87,7 @@ def test_expand_host_rejects_malformed_input():
 
 def test_dispatch_keeps_small_products_on_the_cpu():
     from paper_2002_10083_amd import mcl
-    A = oracle.normalize(planted_graph(2000, 80, s_cap=200, seed=11))
+    A = oracle.normalize(planted_graph(1000, 50, s_cap=80, seed=11))
     R, flops, _ = oracle.expand(A, A)
     total = int(np.asarray(flops).sum())
     assert total < mcl.DISPATCH_GPU_MIN_FLOPS
