@@ -346,6 +346,21 @@ def bench_batched(args, seed=5):
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t
     log("batched: %.2f s, %d calls, not converged %d" % (t_batched, info["calls"], info["not_converged"]))
+    # the other accumulation schedule of the same run: one persistent launch
+    # for all LDS bins per iteration when the tuned policy uses per-bin
+    # launches (and the reverse), same results
+    alt_policy = policy ^ tuning.PERSIST
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Aalt, iters_alt, info_alt = drivers.batched_mcl(A, comp, mcl.default_params(bin_policy=alt_policy,
+                                                                               est_scale=scale, cohen_keys=keys))
+    torch.cuda.synchronize()
+    t_alt = time.perf_counter() - t
+    alt_same = (np.array_equal(iters_alt, iters) and torch.equal(Aalt.colptr, Af.colptr)
+                and torch.equal(Aalt.rowidx, Af.rowidx) and torch.equal(Aalt.val, Af.val))
+    del Aalt
+    log("batched with persistent accumulation %s: %.2f s, identical %s"
+        % ("on" if alt_policy & tuning.PERSIST else "off", t_alt, alt_same))
     ncomp = len(U.comp_ptr) - 1
     sizes = np.diff(U.comp_ptr)
     if args.loop_sample > 0:
@@ -378,7 +393,10 @@ def bench_batched(args, seed=5):
                  {"n": U.ncols, "nnz": U.nnz, "components": ncomp, "batched_s": round(t_batched, 3),
                   "batched_calls": info["calls"], "iterations_max": int(iters.max()),
                   "iterations_mean": round(float(iters.mean()), 2), "not_converged": info["not_converged"],
-                  "policy_key": key,
+                  "policy_key": key, "bin_policy": hex(policy),
+                  "persistent_accumulation": bool(policy & tuning.PERSIST),
+                  "other_schedule": {"persistent_accumulation": bool(alt_policy & tuning.PERSIST),
+                                     "batched_s": round(t_alt, 3), "identical": bool(alt_same)},
                   "loop_components_timed": int(len(pick)),
                   "loop_s": round(t_loop, 3),
                   "loop_mode": "all components" if args.loop_sample <= 0 else

@@ -63,6 +63,8 @@ def main():
         rep.pop("cohen_keys", None)
         policy, rep["persist"] = tuning.decide_persist(run, policy, scale, keys)
         tuning.save_policy(args.key, policy, scale, keys, rep)
+        if args.copy_to:
+            tuning.save_policy(args.key, policy, scale, keys, rep, path=args.copy_to)
         print("tuned", hex(policy), scale, keys, rep["persist"], flush=True)
         return
     if args.workload == "batched":
