@@ -17,6 +17,9 @@ def main():
     ap.add_argument("--persist-only", action="store_true",
                     help="keep the stored launch shapes of --key and only decide whether bins 0-6 "
                          "accumulate in one persistent launch")
+    ap.add_argument("--scale-only", default=None,
+                    help="keep the stored launch shapes and key count of --key and choose the estimate "
+                         "scale (table sizing margin) from this comma-separated list")
     ap.add_argument("--workload", default="iterate", choices=["iterate", "batched"],
                     help="iterate: one fused iteration of the 1M-vertex graph; batched: the first three "
                          "iterations of the 20,000-component graph, all components per call")
@@ -53,6 +56,32 @@ def main():
         return tot
 
     t = time.time()
+    if args.scale_only:
+        import json
+        policy, scale, keys = tuning.load_policy(args.key)
+        with open(tuning.TUNED) as f:
+            rep = json.load(f).get(args.key, {})
+        for k in ("bin_policy", "est_scale", "cohen_keys"):
+            rep.pop(k, None)
+        times = {}
+        for sc in [float(x) for x in args.scale_only.split(",")]:
+            best = None
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st = run(policy, sc, keys)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t1) * 1e3
+                best = dt if best is None else min(best, dt)
+            times[sc] = round(best, 3)
+            print("scale %.2f: %.1f ms (overflow %d)" % (sc, best, st["n_overflow"]), flush=True)
+        scale = min(times, key=lambda k: times[k])
+        rep["scale_ms"] = {str(k): v for k, v in times.items()}
+        tuning.save_policy(args.key, policy, scale, keys, rep)
+        if args.copy_to:
+            tuning.save_policy(args.key, policy, scale, keys, rep, path=args.copy_to)
+        print("tuned", hex(policy), scale, keys, times, flush=True)
+        return
     if args.persist_only:
         policy, scale, keys = tuning.load_policy(args.key)
         with open(tuning.TUNED) as f:

@@ -37,10 +37,13 @@ constexpr int64_t REGION_MASK = ((int64_t)1 << 48) - 1;
 // (load factor 3/4; more keys flag the column as overflowed).
 __host__ __device__ constexpr int bin_slots_c(int b) { return 128 << b; }
 __host__ __device__ constexpr int bin_cap_c(int b) { return (3 * (128 << b)) / 4; }
-// Largest columns (bin 7) in LDS: 64 waves per column, one row group each,
-// in concurrent workgroups -- 512-slot tables per wave up to MP_NARROW keys,
-// 1024-slot tables up to MP_MAX (4/5 of the tables' capacity: headroom for
-// an uneven spread of rows over the waves).  Larger columns use HBM tables.
+// Largest columns (bin 7) in LDS, in concurrent workgroups: up to MP_SMALL
+// keys 32 waves per column with two row groups each, up to MP_NARROW 64
+// waves with one group each, both with 512-slot tables per wave; up to
+// MP_MAX 64 waves with 1024-slot tables (4/5 of the tables' capacity:
+// headroom for an uneven spread of rows over the waves).  Larger columns use
+// HBM tables.
+constexpr int64_t MP_SMALL = (int64_t)32 * ((13 * 512) / 16) * 4 / 5;
 constexpr int64_t MP_NARROW = (int64_t)64 * ((13 * 512) / 16) * 4 / 5;
 constexpr int64_t MP_MAX = (int64_t)64 * ((13 * 1024) / 16) * 4 / 5;
 // Largest row span of a dense-accumulator column (see k_numeric_dense).
@@ -1794,8 +1797,8 @@ __device__ __forceinline__ bool multipass_column(const NumericArgs &a, int64_t j
 
 
 // MP: the launch holds the multi-pass columns of the largest bin together
-// with HBM-table columns, which it skips; 1 = the columns of up to MP_NARROW
-// keys, 2 = the larger ones.
+// with HBM-table columns, which it skips; 3 = the columns of up to MP_SMALL
+// keys, 1 = up to MP_NARROW, 2 = the larger ones.
 template <int NWP, int SW, int P, int MODE, int D, int MP = 0>
 __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
 {
@@ -1819,7 +1822,11 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
     if (idx >= (uint32_t)a.ncols) return;  // whole workgroup
     const int64_t j = a.cols[idx];
     if (dense_column(a, j)) return;  // whole workgroup
-    if (MP && !(multipass_column(a, j) && (MP == 1) == (a.capv[j] <= MP_NARROW))) return;
+    if constexpr (MP != 0) {
+        if (!multipass_column(a, j)) return;  // whole workgroup
+        const int64_t c = a.capv[j];
+        if ((c <= MP_SMALL ? 3 : c <= MP_NARROW ? 1 : 2) != MP) return;
+    }
     if (tid == 0) sh.misc[0] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
@@ -1894,6 +1901,13 @@ template <int MODE>
 __global__ __launch_bounds__(MPW_NW * WAVE) void k_numeric_mpart_wide(NumericArgs a)
 {
     numeric_part_body<MPW_NW, 1024, MPW_P, MODE, 2, 2>(a);
+}
+// up to MP_SMALL keys: 8 workgroups of 4 waves, two row groups per wave
+constexpr int MPS_NW = 4, MPS_P = 8;
+template <int MODE>
+__global__ __launch_bounds__(MPS_NW * WAVE) void k_numeric_mpart_small(NumericArgs a)
+{
+    numeric_part_body<MPS_NW, 512, MPS_P, MODE, 2, 3>(a);
 }
 
 template <int NWP, int SW, int P, int MODE, int D>
@@ -2464,10 +2478,12 @@ void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, si
     const int grid = std::min(nslabs, a.ncols);
     const unsigned g8 = (unsigned)(((a.ncols + 7) / 8) * 8);
     if (mode == MODE_EXPAND) {
+        hipLaunchKernelGGL(k_numeric_mpart_small<MODE_EXPAND>, dim3(g8 * MPS_P), dim3(MPS_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_numeric_mpart<MODE_EXPAND>, dim3(g8 * MPP_P), dim3(MPP_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_numeric_mpart_wide<MODE_EXPAND>, dim3(g8 * MPW_P), dim3(MPW_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_finish_mpass<MODE_EXPAND>, dim3(grid), dim3(1024), 0, st, a, (char *)slab, slab_bytes);
     } else {
+        hipLaunchKernelGGL(k_numeric_mpart_small<MODE_ITERATE>, dim3(g8 * MPS_P), dim3(MPS_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_numeric_mpart<MODE_ITERATE>, dim3(g8 * MPP_P), dim3(MPP_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_numeric_mpart_wide<MODE_ITERATE>, dim3(g8 * MPW_P), dim3(MPW_NW * WAVE), 0, st, a);
         hipLaunchKernelGGL(k_finish_mpass<MODE_ITERATE>, dim3(grid), dim3(1024), 0, st, a, (char *)slab,
