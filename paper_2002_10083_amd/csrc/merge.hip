@@ -52,73 +52,21 @@ __global__ __launch_bounds__(256) void k_merge_ntiles(const DevCSC *__restrict__
 }
 
 // One wave per column: the column of every tile and the first row of every
-// tile.  Boundary k is the smallest row r with at least k * tile elements
-// below it over all lists.  A column of at most MB_STAGE elements is staged
-// in LDS (its lists back to back) and searched 64 candidate rows at a time:
-// lane l counts the elements below the l-th of 64 evenly spaced rows of the
-// current range (one lower_bound per list), the first lane whose count
-// reaches the target narrows the range 64-fold.  Longer columns bisect the
-// row range with the counts taken in global memory (lanes take the lists).
-constexpr int MB_WAVES = 4;      // columns per workgroup
-constexpr int MB_STAGE = 4096;   // staged elements per column
-__global__ __launch_bounds__(MB_WAVES * WAVE) void k_merge_bounds(const DevCSC *__restrict__ parts, int P,
-                                                                  int64_t nrows, int64_t ncols, int64_t tile,
-                                                                  const int64_t *__restrict__ tile_ptr,
-                                                                  int32_t *__restrict__ tile_col,
-                                                                  int32_t *__restrict__ tile_row)
+// tile.  Boundary k is found by a binary search over the row value; each
+// probe counts the elements below it in all lists (lanes take the lists).
+__global__ __launch_bounds__(256) void k_merge_bounds(const DevCSC *__restrict__ parts, int P, int64_t nrows,
+                                                      int64_t ncols, int64_t tile,
+                                                      const int64_t *__restrict__ tile_ptr,
+                                                      int32_t *__restrict__ tile_col,
+                                                      int32_t *__restrict__ tile_row)
 {
-    __shared__ int32_t srows[MB_WAVES][MB_STAGE];
-    __shared__ int32_t soff[MB_WAVES][MT_MAX_PARTS + 1];
-    int32_t *rows = srows[threadIdx.x / WAVE];
-    int32_t *off = soff[threadIdx.x / WAVE];
-    const int64_t nw = (int64_t)gridDim.x * MB_WAVES;
-    for (int64_t j = (int64_t)blockIdx.x * MB_WAVES + threadIdx.x / WAVE; j < ncols; j += nw) {
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; j < ncols; j += nw) {
         const int64_t t0 = tile_ptr[j];
         const int T = (int)(tile_ptr[j + 1] - t0);
         for (int k = lane(); k < T; k += WAVE) {
             tile_col[t0 + k] = (int32_t)j;
             if (k == 0) tile_row[t0] = 0;
-        }
-        if (T == 1) continue;  // whole wave
-        // the column's length in every list, then its total
-        int64_t mtot = 0;
-        for (int q = lane(); q < P; q += WAVE) mtot += parts[q].colptr[j + 1] - parts[q].colptr[j];
-        mtot = wave_sum_i64(mtot);
-        if (mtot <= MB_STAGE) {
-            if (lane() == 0) {
-                int o = 0;
-                for (int q = 0; q < P; ++q) {
-                    off[q] = o;
-                    o += (int)(parts[q].colptr[j + 1] - parts[q].colptr[j]);
-                }
-                off[P] = o;
-            }
-            group_sync<WAVE>();
-            for (int q = 0; q < P; ++q) {
-                const int o = off[q], nq = off[q + 1] - o;
-                const int32_t *src = parts[q].rowidx + parts[q].colptr[j];
-                for (int i = lane(); i < nq; i += WAVE) rows[o + i] = src[i];
-            }
-            group_sync<WAVE>();
-            for (int k = 1; k < T; ++k) {
-                const int64_t target = (int64_t)k * tile;
-                int64_t lo = 0, hi = nrows;  // the answer lies in [lo, hi]
-                while (lo < hi) {
-                    const int64_t cand = lo + ((hi - lo) * (lane() + 1)) / WAVE;  // lane 63: hi
-                    int64_t c = 0;
-                    for (int q = 0; q < P; ++q)
-                        c += lower_bound_i32(rows + off[q], off[q + 1] - off[q], (int32_t)cand);
-                    const uint64_t ok = ballot(c >= target);  // lane 63 always (count at nrows = mtot)
-                    const int l = __ffsll((long long)ok) - 1;
-                    const int64_t nhi = readlane_i64(cand, l);
-                    const int64_t nlo = l == 0 ? lo : readlane_i64(cand, l - 1) + 1;
-                    lo = nlo;
-                    hi = nhi;
-                }
-                if (lane() == 0) tile_row[t0 + k] = (int32_t)lo;
-            }
-            group_sync<WAVE>();  // the staged rows are read before the next column overwrites them
-            continue;
         }
         for (int k = 1; k < T; ++k) {
             const int64_t target = (int64_t)k * tile;
@@ -253,8 +201,8 @@ void launch_merge_bounds(const DevCSC *parts, int nparts, int64_t nrows, int64_t
                          int32_t *tile_col, int32_t *tile_row, hipStream_t st)
 {
     if (ncols <= 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>((ncols + MB_WAVES - 1) / MB_WAVES, 65536);
-    hipLaunchKernelGGL(k_merge_bounds, dim3(g), dim3(MB_WAVES * WAVE), 0, st, parts, nparts, nrows, ncols,
+    const unsigned g = (unsigned)std::min<int64_t>((ncols + 3) / 4, 65536);
+    hipLaunchKernelGGL(k_merge_bounds, dim3(g), dim3(256), 0, st, parts, nparts, nrows, ncols,
                        merge_tile_elems(nparts), tile_ptr, tile_col, tile_row);
 }
 

@@ -295,19 +295,65 @@ def same_block(Abig: "mcl.DeviceCSC", c0: int, c1: int, Ablk: "mcl.DeviceCSC") -
             and torch.equal(Abig.val[p0:p1], Ablk.val))
 
 
-def run_mcl(A: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 100):
+def save_checkpoint(path: str, A: "mcl.DeviceCSC", iteration: int, converged: bool = False):
+    """Writes the iterate, the number of iterations done and whether the run
+    has converged to `path` (numpy .npz): first to a temporary file next to
+    it, then renamed over it, so an interrupted run never leaves a partial
+    checkpoint."""
+    import os
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, nrows=A.nrows, ncols=A.ncols, iteration=iteration, converged=converged,
+             colptr=A.colptr.cpu().numpy(), rowidx=A.rowidx.cpu().numpy(), val=A.val.cpu().numpy())
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str):
+    """(iterate on the device, iterations done, converged) from
+    save_checkpoint's file."""
+    with np.load(path, allow_pickle=False) as z:
+        A = mcl.DeviceCSC(int(z["nrows"]), int(z["ncols"]), torch.from_numpy(z["colptr"]).cuda(),
+                          torch.from_numpy(z["rowidx"]).cuda(), torch.from_numpy(z["val"]).cuda())
+        return A, int(z["iteration"]), bool(z["converged"])
+
+
+def run_mcl(A: "mcl.DeviceCSC", params=None, tol: float = 1e-9, max_iter: int = 100, log_path: str = None,
+            checkpoint_path: str = None, checkpoint_every: int = 1, resume: bool = False):
     """Alg. 1 on the GPU from a column-stochastic A: iterate until the change
-    drops below `tol` (or `max_iter` iterations), then label the connected
-    components of the final pattern.  Returns (A_final, iterations, labels,
-    ncomp, converged); labels is a device int32 tensor (smallest vertex id of
-    each vertex's cluster)."""
+    drops below `tol` (or `max_iter` iterations in all), then label the
+    connected components of the final pattern.  Returns (A_final,
+    iterations, labels, ncomp, converged); labels is a device int32 tensor
+    (smallest vertex id of each vertex's cluster).
+
+    log_path: one JSON line per iteration is appended (iteration, change,
+    flops, product and kept nnz, overflowed and HBM-table columns, phases,
+    milliseconds).  checkpoint_path: every `checkpoint_every` iterations the
+    iterate and the iteration count are saved there; with resume=True a run
+    starts from that checkpoint when it exists (A is then not used) and ends
+    bit-identical to an uninterrupted run."""
+    import json
+    import os
     it = 0
     converged = False
-    while it < max_iter:
-        A, change, _ = mcl.iterate(A, params, iteration=it)
-        it += 1
-        if change < tol:
-            converged = True
-            break
+    if resume and checkpoint_path and os.path.exists(checkpoint_path):
+        A, it, converged = load_checkpoint(checkpoint_path)
+    logf = open(log_path, "a") if log_path else None
+    try:
+        while it < max_iter and not converged:
+            A, change, st = mcl.iterate(A, params, iteration=it)
+            it += 1
+            if logf:
+                logf.write(json.dumps({"iteration": it, "change": change, "flops": st["flops"],
+                                       "nnz_product": st["nnz_product"], "nnz_kept": st["nnz_kept"],
+                                       "n_overflow": st["n_overflow"], "n_global": st["n_global"],
+                                       "n_phases": st["n_phases"], "t_total_ms": round(st["t_total_ms"], 3)})
+                           + "\n")
+                logf.flush()
+            if change < tol:
+                converged = True
+            if checkpoint_path and (converged or it % max(1, checkpoint_every) == 0 or it == max_iter):
+                save_checkpoint(checkpoint_path, A, it, converged)
+    finally:
+        if logf:
+            logf.close()
     labels, ncomp = mcl.components(A)
     return A, it, labels, ncomp, converged

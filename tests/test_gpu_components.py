@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from mclgen import CSC, config0_graph, planted_components, random_csc, random_symmetric_graph
+from mclgen import CSC, config0_graph, planted_components, planted_graph, random_csc, random_symmetric_graph
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -88,3 +88,28 @@ def test_mcl_clusters_on_gpu_match_oracle(mcl):
     assert np.array_equal(lab, lab_o)                            # the oracle's own run
     assert nc == len(np.unique(lab_o))
     assert abs(it - it_o) <= 1
+
+
+def test_run_mcl_checkpoint_resume_and_log(mcl, tmp_path):
+    """An MCL run interrupted after three iterations and resumed from its
+    checkpoint ends bit-identical to an uninterrupted run; the per-iteration
+    log holds one line per iteration done."""
+    import json
+    from paper_2002_10083_amd import drivers
+    A = oracle.normalize(planted_graph(5000, 200, s_cap=400, seed=41))
+    ref, it_ref, lab_ref, nc_ref, conv_ref = drivers.run_mcl(mcl.DeviceCSC.from_host(A), max_iter=100)
+    assert conv_ref and it_ref > 3
+    ck, log = str(tmp_path / "ck.npz"), str(tmp_path / "log.jsonl")
+    _, it1, _, _, conv1 = drivers.run_mcl(mcl.DeviceCSC.from_host(A), max_iter=3, log_path=log,
+                                          checkpoint_path=ck, checkpoint_every=2)
+    assert it1 == 3 and not conv1
+    G, it2, lab, nc, conv = drivers.run_mcl(None, max_iter=100, log_path=log, checkpoint_path=ck, resume=True)
+    assert (it2, nc, conv) == (it_ref, nc_ref, conv_ref)
+    assert torch.equal(G.colptr, ref.colptr) and torch.equal(G.rowidx, ref.rowidx) and torch.equal(G.val, ref.val)
+    assert torch.equal(lab, lab_ref)
+    lines = [json.loads(l) for l in open(log)]
+    assert [d["iteration"] for d in lines] == list(range(1, it_ref + 1))
+    assert lines[-1]["change"] < 1e-9 <= lines[-2]["change"]
+    # resuming a finished run does no further iteration
+    _, it3, _, _, conv3 = drivers.run_mcl(None, max_iter=100, checkpoint_path=ck, resume=True)
+    assert (it3, conv3) == (it_ref, True)
