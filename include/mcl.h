@@ -223,9 +223,11 @@ int mcl_components_noalloc(const mcl_csc *A, int32_t *labels, int64_t *ncomp, vo
  * HOST array of descriptors whose arrays are device pointers; 1 <= nparts <=
  * 256, else MCL_EINVAL).  A sorted multiway merge: each input column is read
  * as an ascending run of rows, equal rows are summed in array order,
- * (((p0 + p1) + p2) + ...), over the parts that hold the row.  Workspace is
- * O(ncols + nnz(C) / 2000); the output is sized by a counting pass, so the
- * peak memory is the inputs plus C.  stats: nnz_product = nnz_kept = nnz(C),
+ * (((p0 + p1) + p2) + ...), over the parts that hold the row.  Columns are
+ * cut into tiles of at most 2,048 merged elements; workspace is O(ncols) plus
+ * 280 bytes per tile (its bounds and the counting pass's owner flags), and
+ * the output is sized by that counting pass, so the peak memory is the
+ * inputs plus C plus the workspace.  stats: nnz_product = nnz_kept = nnz(C),
  * t_merge_ms, bin_cols[7] = the number of merge tiles. */
 int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C,
                        const mcl_allocator *alloc, void *stream, mcl_stats *stats);

@@ -1136,11 +1136,12 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
             int64_t *tile_cnt = mem.ws<int64_t>(ntiles);
             int64_t *tile_off = mem.ws<int64_t>(ntiles + 1);
             int32_t *err = mem.ws<int32_t>(1);
+            uint32_t *obits = mem.ws<uint32_t>(mcl::merge_owner_words(ntiles));
             HIPC(hipMemsetAsync(err, 0, sizeof(int32_t), mem.st));
             mcl::launch_merge_bounds(dparts, nparts, nrows, n, tile_ptr, tile_col, tile_row, mem.st);
             // count pass, output offsets, fill pass
             mcl::launch_merge_tiles(false, dparts, nparts, nrows, ntiles, tile_ptr, tile_col, tile_row, tile_cnt,
-                                    nullptr, nullptr, nullptr, err, mem.st);
+                                    nullptr, nullptr, nullptr, obits, err, mem.st);
             int64_t *tmp2 = mem.ws<int64_t>(mcl::exscan_tmp_elems(ntiles));
             mcl::launch_exscan_i64(tile_cnt, tile_off, ntiles, tmp2, mem.st);
             int32_t herr = 0;
@@ -1152,7 +1153,7 @@ int mcl_merge_partials(const mcl_csc *parts, int32_t nparts, mcl_csc *C, const m
             val = mem.out<double>(nnz);
             mcl::launch_merge_colptr(n, tile_ptr, tile_off, colptr, mem.st);
             mcl::launch_merge_tiles(true, dparts, nparts, nrows, ntiles, tile_ptr, tile_col, tile_row, nullptr,
-                                    tile_off, row, val, err, mem.st);
+                                    tile_off, row, val, obits, err, mem.st);
         }
         HIPC(hipGetLastError());
         tm.mark();

@@ -184,10 +184,12 @@ int64_t merge_tile_elems(int nparts);                  // target elements per ti
 void launch_merge_ntiles(const DevCSC *parts, int nparts, int64_t ncols, int64_t *ntile, hipStream_t st);
 void launch_merge_bounds(const DevCSC *parts, int nparts, int64_t nrows, int64_t ncols, const int64_t *tile_ptr,
                          int32_t *tile_col, int32_t *tile_row, hipStream_t st);
+// owner-flag workspace of the count pass, read by the fill pass (uint32 words)
+int64_t merge_owner_words(int64_t ntiles);
 void launch_merge_tiles(bool fill, const DevCSC *parts, int nparts, int64_t nrows, int64_t ntiles,
                         const int64_t *tile_ptr, const int32_t *tile_col, const int32_t *tile_row,
                         int64_t *tile_cnt, const int64_t *tile_off, int32_t *out_row, double *out_val,
-                        int32_t *err, hipStream_t st);
+                        uint32_t *obits, int32_t *err, hipStream_t st);
 void launch_merge_colptr(int64_t ncols, const int64_t *tile_ptr, const int64_t *tile_off, int64_t *colptr,
                          hipStream_t st);
 

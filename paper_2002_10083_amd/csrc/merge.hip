@@ -23,6 +23,7 @@ namespace mcl {
 
 constexpr int MT_NT = 256;    // threads per tile
 constexpr int MT_CAP = 2048;  // elements per tile (LDS)
+constexpr int MT_WORDS = MT_CAP / 32;  // owner-flag words per tile
 
 int merge_max_parts() { return MT_MAX_PARTS; }
 int64_t merge_tile_elems(int nparts) { return (int64_t)MT_CAP - nparts; }
@@ -87,8 +88,10 @@ __global__ __launch_bounds__(256) void k_merge_bounds(const DevCSC *__restrict__
     }
 }
 
-// One workgroup per tile.  COUNT: tile_cnt[t] = owners of the tile.  FILL:
-// the owners' rows and summed values at tile_off[t] + their rank.
+// One workgroup per tile.  COUNT: tile_cnt[t] = owners of the tile, and
+// the owner flag of every element as a bit in obits[t * MT_WORDS ...].
+// FILL: the owners' rows and summed values at tile_off[t] + their rank
+// (the flags are read back, not recomputed).
 template <bool FILL>
 __global__ __launch_bounds__(MT_NT) void k_merge_tile(const DevCSC *__restrict__ parts, int P, int64_t nrows,
                                                       const int64_t *__restrict__ tile_ptr,
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(MT_NT) void k_merge_tile(const DevCSC *__restrict__
                                                       int64_t *__restrict__ tile_cnt,
                                                       const int64_t *__restrict__ tile_off,
                                                       int32_t *__restrict__ out_row, double *__restrict__ out_val,
-                                                      int32_t *__restrict__ err)
+                                                      uint32_t *__restrict__ obits, int32_t *__restrict__ err)
 {
     __shared__ int32_t rows[MT_CAP];
     __shared__ int32_t pre[MT_CAP + 1];
@@ -138,18 +141,34 @@ __global__ __launch_bounds__(MT_NT) void k_merge_tile(const DevCSC *__restrict__
         for (int i = tid; i < nq; i += MT_NT) rows[o + i] = src[i];
     }
     __syncthreads();
-    // owners: no earlier list holds the row (consecutive lanes take
-    // consecutive elements, so the row reads are free of bank conflicts)
-    for (int idx = tid; idx < m; idx += MT_NT) {
-        const int p = lower_bound_i32(segoff + 1, P, idx + 1);  // run holding idx
-        const int32_t r = rows[idx];
-        bool owner = true;
-        for (int q = 0; q < p && owner; ++q) {
-            const int o = segoff[q], nq = segoff[q + 1] - o;
-            const int lb = lower_bound_i32(rows + o, nq, r);
-            owner = !(lb < nq && rows[o + lb] == r);
+    uint32_t *tbits = obits + t * MT_WORDS;
+    if constexpr (FILL) {
+        for (int idx = tid; idx < m; idx += MT_NT) pre[idx] = (int32_t)((tbits[idx >> 5] >> (idx & 31)) & 1u);
+    } else {
+        // owners: no earlier list holds the row (consecutive lanes take
+        // consecutive elements, so the row reads are free of bank conflicts)
+        for (int i0 = 0; i0 < m; i0 += MT_NT) {
+            const int idx = i0 + tid;
+            bool owner = false;
+            if (idx < m) {
+                const int p = lower_bound_i32(segoff + 1, P, idx + 1);  // run holding idx
+                const int32_t r = rows[idx];
+                owner = true;
+                for (int q = 0; q < p && owner; ++q) {
+                    const int o = segoff[q], nq = segoff[q + 1] - o;
+                    const int lb = lower_bound_i32(rows + o, nq, r);
+                    owner = !(lb < nq && rows[o + lb] == r);
+                }
+                pre[idx] = owner ? 1 : 0;
+            }
+            // the wave's 64 consecutive elements: two words of flags
+            const uint64_t mk = ballot(owner);
+            const int w0 = (i0 + (tid & ~(WAVE - 1))) >> 5;
+            if (lane() == 0 && w0 * 32 < m) {
+                tbits[w0] = (uint32_t)mk;
+                tbits[w0 + 1] = (uint32_t)(mk >> 32);
+            }
         }
-        pre[idx] = owner ? 1 : 0;
     }
     __syncthreads();
     const int owners = block_exscan<MT_NT>(pre, m, wsum);
@@ -206,18 +225,20 @@ void launch_merge_bounds(const DevCSC *parts, int nparts, int64_t nrows, int64_t
                        merge_tile_elems(nparts), tile_ptr, tile_col, tile_row);
 }
 
+int64_t merge_owner_words(int64_t ntiles) { return ntiles * MT_WORDS; }
+
 void launch_merge_tiles(bool fill, const DevCSC *parts, int nparts, int64_t nrows, int64_t ntiles,
                         const int64_t *tile_ptr, const int32_t *tile_col, const int32_t *tile_row,
                         int64_t *tile_cnt, const int64_t *tile_off, int32_t *out_row, double *out_val,
-                        int32_t *err, hipStream_t st)
+                        uint32_t *obits, int32_t *err, hipStream_t st)
 {
     if (ntiles <= 0) return;
     if (fill)
         hipLaunchKernelGGL(k_merge_tile<true>, dim3((unsigned)ntiles), dim3(MT_NT), 0, st, parts, nparts, nrows,
-                           tile_ptr, tile_col, tile_row, tile_cnt, tile_off, out_row, out_val, err);
+                           tile_ptr, tile_col, tile_row, tile_cnt, tile_off, out_row, out_val, obits, err);
     else
         hipLaunchKernelGGL(k_merge_tile<false>, dim3((unsigned)ntiles), dim3(MT_NT), 0, st, parts, nparts,
-                           nrows, tile_ptr, tile_col, tile_row, tile_cnt, tile_off, out_row, out_val, err);
+                           nrows, tile_ptr, tile_col, tile_row, tile_cnt, tile_off, out_row, out_val, obits, err);
 }
 
 void launch_merge_colptr(int64_t ncols, const int64_t *tile_ptr, const int64_t *tile_off, int64_t *colptr,
