@@ -289,7 +289,7 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
                 HIPC(hipEventCreate(&em));
                 HIPC(hipEventRecord(e0, mem.st));
             }
-            uint32_t *next = mem.ws<uint32_t>(1);
+            uint32_t *next = mem.ws<uint32_t>(mcl::PERSIST_QUEUES);
             mcl::launch_numeric_persist(mode, a, lists, counts, dense_bin, next, mem.st, em);
             HIPC(hipGetLastError());
             if (timed) {

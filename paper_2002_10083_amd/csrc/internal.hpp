@@ -57,12 +57,14 @@ constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced
 constexpr uint32_t POLICY_PERSIST = 1u << 28;
 // Work schedule of the persistent accumulation: entry e covers the columns
 // of bin `bin[e]` (at `off[e]` in the bin lists), 2^parts[e] items per
-// column; items [first[e], first[e + 1]) belong to entry e (fewer than 2^31
-// items in all).
+// column.  Column c of an entry belongs to queue c % PERSIST_QUEUES; in
+// queue x, items [qfirst[x][e], qfirst[x][e + 1]) belong to entry e (fewer
+// than 2^30 items in all).
+constexpr int PERSIST_QUEUES = 8;
 struct PersistSched {
     int32_t n;
     int32_t bin[7], parts[7], off[7];
-    int64_t first[8];
+    int32_t qfirst[PERSIST_QUEUES][8];
 };
 // the sliced kernels index the sliced copy of A (and its sentinel) with 32-bit entry indices
 constexpr int64_t SLICE_MAX_NNZ = (int64_t{1} << 32) - 2;
@@ -78,7 +80,7 @@ size_t mpass_slab_bytes();
 bool persist_fits(const int32_t counts[8]);
 // the persistent accumulation of bins 0-6 (dense launches first, finishing
 // launches after; mid, nullable, is recorded after the accumulation);
-// `next` is a device counter (zeroed here)
+// `next` points to PERSIST_QUEUES device counters (zeroed here)
 void launch_numeric_persist(NumericMode mode, const NumericArgs &a, const int32_t *lists, const int32_t counts[8],
                             const int64_t *dense_bin, uint32_t *next, hipStream_t st, hipEvent_t mid);
 void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,

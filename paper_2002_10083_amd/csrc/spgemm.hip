@@ -2037,13 +2037,17 @@ static void launch_part(const NumericArgs &a, hipStream_t st, hipEvent_t mid)
 // keys and values, unsorted, to the column's temp slot as the split kernels
 // do.  Items are numbered in schedule order -- the bins in the order the
 // schedule lists them, a bin's columns in list order, a column's parts one
-// after another -- and every wave takes PERSIST_BATCH consecutive items at a
-// time from one work counter until none is left, so the columns of
-// every bin (and, in a batched iteration, of every component) share one
-// launch with no tail between bins.  The waves of a workgroup never
+// after another.  The columns are dealt to eight queues, one per XCD (column
+// c of a bin to queue c % 8), so the parts of a column run on one XCD and
+// fetch the column's step metadata into one L2; a wave takes PERSIST_BATCH
+// consecutive items at a time from its XCD's queue, then from the others,
+// until none is left, so the columns of every bin (and, in a batched
+// iteration, of every component) share one launch with no tail between
+// bins.  The waves of a workgroup never
 // synchronise with each other.  The finishing launches of every bin follow.
 // ---------------------------------------------------------------------------
 constexpr int PERSIST_BATCH = 4;
+static_assert(PERSIST_QUEUES == 8, "one work queue per XCD");
 
 void launch_numeric_dense(NumericMode mode, const NumericArgs &a, hipStream_t st);
 
@@ -2096,9 +2100,8 @@ __device__ __forceinline__ void part_wave(const NumericArgs &a, int64_t j, int p
 // spills (measured on the batched iterations: 0.6 % faster than the
 // unconstrained 92 registers at five waves).
 template <int MODE>
-__global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(6))) void k_numeric_persist(NumericArgs a, PersistSched s,
-                                                              const int32_t *__restrict__ lists,
-                                                              uint32_t *__restrict__ next)
+__global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(6))) void k_numeric_persist(
+    NumericArgs a, PersistSched s, const int32_t *__restrict__ lists, uint32_t *__restrict__ next)
 {
     struct alignas(16) W {
         double val[512];
@@ -2108,28 +2111,35 @@ __global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(6))) v
     };
     __shared__ W ws[4];
     W &me = ws[threadIdx.x / WAVE];
-    const uint32_t total = (uint32_t)s.first[s.n];
-    for (;;) {
-        uint32_t i0 = 0;
-        if (lane() == 0) i0 = atomicAdd(next, (uint32_t)PERSIST_BATCH);
-        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)i0);
-        if (b0 >= total) return;  // whole wave
-        const uint32_t b1 = min(b0 + (uint32_t)PERSIST_BATCH, total);
-        for (uint32_t i = b0; i < b1; ++i) {
-            int e = 0;
-            while (i >= (uint32_t)s.first[e + 1]) ++e;
-            const uint32_t loc = i - (uint32_t)s.first[e];
-            const int lg = s.parts[e];  // log2 of the parts per column
-            const uint32_t q = loc >> lg;
-            const int p = (int)(loc & ((1u << lg) - 1));
-            const int64_t j = lists[s.off[e] + q];
-            if (dense_column(a, j)) continue;  // the dense kernels own it
-            switch (lg) {
-            case 0: part_wave<MODE, 0>(a, j, p, me.key, me.val, me.misc, me.dm); break;
-            case 1: part_wave<MODE, 1>(a, j, p, me.key, me.val, me.misc, me.dm); break;
-            case 2: part_wave<MODE, 2>(a, j, p, me.key, me.val, me.misc, me.dm); break;
-            case 3: part_wave<MODE, 3>(a, j, p, me.key, me.val, me.misc, me.dm); break;
-            default: part_wave<MODE, 4>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+    // workgroups are dealt to the XCDs in turn: a wave serves the queue of
+    // its own XCD first, then helps with the others
+    const int x0 = (int)(blockIdx.x % PERSIST_QUEUES);
+    for (int t = 0; t < PERSIST_QUEUES; ++t) {
+        const int x = (x0 + t) % PERSIST_QUEUES;
+        const int32_t *first = s.qfirst[x];
+        const uint32_t total = (uint32_t)first[s.n];
+        for (;;) {
+            uint32_t i0 = 0;
+            if (lane() == 0) i0 = atomicAdd(&next[x], (uint32_t)PERSIST_BATCH);
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)i0);
+            if (b0 >= total) break;  // whole wave: this queue is done
+            const uint32_t b1 = min(b0 + (uint32_t)PERSIST_BATCH, total);
+            for (uint32_t i = b0; i < b1; ++i) {
+                int e = 0;
+                while (i >= (uint32_t)first[e + 1]) ++e;
+                const uint32_t loc = i - (uint32_t)first[e];
+                const int lg = s.parts[e];  // log2 of the parts per column
+                const uint32_t cq = loc >> lg;  // the queue's cq-th column of the entry
+                const int p = (int)(loc & ((1u << lg) - 1));
+                const int64_t j = lists[s.off[e] + x + PERSIST_QUEUES * cq];
+                if (dense_column(a, j)) continue;  // the dense kernels own it
+                switch (lg) {
+                case 0: part_wave<MODE, 0>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+                case 1: part_wave<MODE, 1>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+                case 2: part_wave<MODE, 2>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+                case 3: part_wave<MODE, 3>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+                default: part_wave<MODE, 4>(a, j, p, me.key, me.val, me.misc, me.dm); break;
+                }
             }
         }
     }
@@ -2162,18 +2172,28 @@ void launch_numeric_persist(NumericMode mode, const NumericArgs &a0, const int32
         a.ncols = counts[b];
         launch_numeric_dense(mode, a, st);
     }
-    // schedule: the heaviest bins first
+    // schedule: the heaviest bins first; column c of a bin goes to queue
+    // c % PERSIST_QUEUES, whose items are numbered entry by entry
     PersistSched s{};
-    s.first[0] = 0;
     for (int b = NUM_LDS_BINS - 1; b >= 0; --b) {
         if (counts[b] == 0) continue;
         const int e = s.n++;
         s.bin[e] = b;
         s.parts[e] = split_parts_log2(b);
         s.off[e] = off[b];
-        s.first[e + 1] = s.first[e] + ((int64_t)counts[b] << s.parts[e]);
     }
-    for (int e = s.n + 1; e <= NUM_LDS_BINS; ++e) s.first[e] = s.first[s.n];
+    int64_t items = 0;
+    for (int x = 0; x < PERSIST_QUEUES; ++x) {
+        int64_t f = 0;
+        s.qfirst[x][0] = 0;
+        for (int e = 0; e < s.n; ++e) {
+            const int64_t cols = counts[s.bin[e]] > x ? (counts[s.bin[e]] - x + PERSIST_QUEUES - 1) / PERSIST_QUEUES : 0;
+            f += cols << s.parts[e];
+            s.qfirst[x][e + 1] = (int32_t)f;
+        }
+        for (int e = s.n + 1; e <= NUM_LDS_BINS; ++e) s.qfirst[x][e] = (int32_t)f;
+        items += f;
+    }
     if (s.n > 0) {
         static unsigned resident[2] = {0, 0};
         const int mi = mode == MODE_EXPAND ? 0 : 1;
@@ -2188,10 +2208,9 @@ void launch_numeric_persist(NumericMode mode, const NumericArgs &a0, const int32
                                                                    0);
             resident[mi] = (unsigned)std::max(1, per_cu) * (unsigned)std::max(1, cus);
         }
-        const int64_t items = s.first[s.n];
         const unsigned grid =
             (unsigned)std::min<int64_t>(resident[mi], (items + 4 * PERSIST_BATCH - 1) / (4 * PERSIST_BATCH));
-        (void)hipMemsetAsync(next, 0, sizeof(uint32_t), st);
+        (void)hipMemsetAsync(next, 0, PERSIST_QUEUES * sizeof(uint32_t), st);
         if (mode == MODE_EXPAND)
             hipLaunchKernelGGL(k_numeric_persist<MODE_EXPAND>, dim3(grid), dim3(4 * WAVE), 0, st, a0, s, lists, next);
         else
