@@ -56,8 +56,10 @@ extern "C" {
 #define MCL_ENOMEM (-2)   /* the allocator returned NULL */
 #define MCL_EHIP (-3)     /* HIP runtime error (text in mcl_last_error) */
 
-/* bin_policy flag: one persistent accumulation launch for LDS bins 0-6 */
+/* bin_policy flags: one persistent accumulation launch for LDS bins 0-6,
+ * and its queue order (lightest bins first instead of heaviest) */
 #define MCL_POLICY_PERSIST (1 << 28)
+#define MCL_POLICY_LIGHT_FIRST (1 << 29)
 
 /* Output-size estimator used to size the per-column hash tables. */
 #define MCL_EST_BOUND 0   /* exact-safe bound min(flops_j, row span_j) */
@@ -94,8 +96,9 @@ typedef struct {
     int32_t bin_policy;      /* launch shape per table bin, 4 bits per bin (0 = default); bit 28
                                 (MCL_POLICY_PERSIST): accumulate the columns of all LDS bins
                                 (0-6) in one persistent launch whose waves take (column, part)
-                                work items from a queue, heaviest bins first, then finish each
-                                bin (sort, epilogue) -- same results */
+                                work items from per-XCD queues, heaviest bins first (bit 29,
+                                MCL_POLICY_LIGHT_FIRST: lightest first), then finish each bin
+                                (sort, epilogue) -- same results */
     float *est_out;          /* optional device float[ncols]: the estimate used per column */
     int64_t *nnz_out;        /* optional device int64[ncols]: exact nnz of each product column */
     int64_t phase_bytes;     /* mcl_iterate: bound on the product's temporary storage; when the

@@ -290,7 +290,8 @@ void run_bins(Mem &mem, mcl::NumericMode mode, mcl::NumericArgs a, const int32_t
                 HIPC(hipEventRecord(e0, mem.st));
             }
             uint32_t *next = mem.ws<uint32_t>(mcl::PERSIST_QUEUES);
-            mcl::launch_numeric_persist(mode, a, lists, counts, dense_bin, next, mem.st, em);
+            mcl::launch_numeric_persist(mode, a, lists, counts, dense_bin, next,
+                                        (policy & mcl::POLICY_LIGHT_FIRST) != 0, mem.st, em);
             HIPC(hipGetLastError());
             if (timed) {
                 HIPC(hipEventRecord(e1, mem.st));

@@ -53,8 +53,10 @@ struct NumericArgs {
 
 // ---- spgemm.hip
 constexpr int SLICE_GROUPS = 64;                     // row groups of the sliced source layout
-// bin_policy bit: accumulate LDS bins 0-6 in one persistent launch
+// bin_policy bits: accumulate LDS bins 0-6 in one persistent launch; with
+// it, queue the lightest bins first instead of the heaviest
 constexpr uint32_t POLICY_PERSIST = 1u << 28;
+constexpr uint32_t POLICY_LIGHT_FIRST = 1u << 29;
 // Work schedule of the persistent accumulation: entry e covers the columns
 // of bin `bin[e]` (at `off[e]` in the bin lists), 2^parts[e] items per
 // column.  Column c of an entry belongs to queue c % PERSIST_QUEUES; in
@@ -82,7 +84,8 @@ bool persist_fits(const int32_t counts[8]);
 // launches after; mid, nullable, is recorded after the accumulation);
 // `next` points to PERSIST_QUEUES device counters (zeroed here)
 void launch_numeric_persist(NumericMode mode, const NumericArgs &a, const int32_t *lists, const int32_t counts[8],
-                            const int64_t *dense_bin, uint32_t *next, hipStream_t st, hipEvent_t mid);
+                            const int64_t *dense_bin, uint32_t *next, bool light_first, hipStream_t st,
+                            hipEvent_t mid);
 void launch_numeric_mpass(NumericMode mode, const NumericArgs &a, void *slab, size_t slab_bytes, int nslabs,
                           hipStream_t st);
 void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64_t c0, int64_t c1,

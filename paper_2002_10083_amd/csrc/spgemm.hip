@@ -2156,7 +2156,8 @@ bool persist_fits(const int32_t counts[8])
 }
 
 void launch_numeric_persist(NumericMode mode, const NumericArgs &a0, const int32_t *lists, const int32_t counts[8],
-                            const int64_t *dense_bin, uint32_t *next, hipStream_t st, hipEvent_t mid)
+                            const int64_t *dense_bin, uint32_t *next, bool light_first, hipStream_t st,
+                            hipEvent_t mid)
 {
     NumericArgs a = a0;
     int32_t off[NUM_LDS_BINS];
@@ -2172,10 +2173,12 @@ void launch_numeric_persist(NumericMode mode, const NumericArgs &a0, const int32
         a.ncols = counts[b];
         launch_numeric_dense(mode, a, st);
     }
-    // schedule: the heaviest bins first; column c of a bin goes to queue
-    // c % PERSIST_QUEUES, whose items are numbered entry by entry
+    // schedule: the heaviest bins first (or, by the policy, the lightest);
+    // column c of a bin goes to queue c % PERSIST_QUEUES, whose items are
+    // numbered entry by entry
     PersistSched s{};
-    for (int b = NUM_LDS_BINS - 1; b >= 0; --b) {
+    for (int k = 0; k < NUM_LDS_BINS; ++k) {
+        const int b = light_first ? k : NUM_LDS_BINS - 1 - k;
         if (counts[b] == 0) continue;
         const int e = s.n++;
         s.bin[e] = b;

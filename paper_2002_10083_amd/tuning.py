@@ -61,18 +61,21 @@ def save_policy(key: str, policy: int, scale: float, keys: int, info: dict, path
         json.dump(d, f, indent=1, sort_keys=True)
 
 
-#: bin_policy flag: accumulate LDS bins 0-6 in one persistent launch
+#: bin_policy flags: accumulate LDS bins 0-6 in one persistent launch, and
+#: its queue order (lightest bins first instead of heaviest)
 PERSIST = 1 << 28
+LIGHT_FIRST = 1 << 29
 
 
 def decide_persist(run, policy: int, scale: float, keys: int, reps: int = 2, log=print):
-    """Times the stored launch shapes with and without the persistent
-    accumulation (whole-step wall time, best of `reps`); returns the faster
-    policy and both times."""
+    """Times the stored launch shapes with per-bin launches and with the
+    persistent accumulation in both queue orders (whole-step wall time, best
+    of `reps`); returns the fastest policy and the three times."""
     import torch
+    base = policy & ~(PERSIST | LIGHT_FIRST)
+    trials = {"off_ms": base, "on_ms": base | PERSIST, "on_light_first_ms": base | PERSIST | LIGHT_FIRST}
     ms = {}
-    for on in (False, True):
-        pol = (policy | PERSIST) if on else (policy & ~PERSIST)
+    for name, pol in trials.items():
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -81,10 +84,10 @@ def decide_persist(run, policy: int, scale: float, keys: int, reps: int = 2, log
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t) * 1e3
             best = dt if best is None else min(best, dt)
-        ms[on] = best
-        log("persistent accumulation %s: %.1f ms" % ("on" if on else "off", best))
-    pol = (policy | PERSIST) if ms[True] < ms[False] else (policy & ~PERSIST)
-    return pol, {"off_ms": round(ms[False], 3), "on_ms": round(ms[True], 3)}
+        ms[name] = round(best, 3)
+        log("persistent accumulation %s: %.1f ms" % (name[:-3].replace("_", " "), best))
+    win = min(ms, key=lambda k: ms[k])
+    return trials[win], ms
 
 
 def candidates_from(key: str, slack: float = 1.3):

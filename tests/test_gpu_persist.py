@@ -1,8 +1,8 @@
 """The persistent accumulation (bin_policy bit 28: one launch for the columns
-of LDS bins 0-6, waves taking (column, part) items from a queue, then the
-finishing launches of every bin) gives the same bytes as the per-bin
-launches and matches the oracle: single graphs, expand mode, forced
-overflow, dense-accumulator columns and the batched form."""
+of LDS bins 0-6, waves taking (column, part) items from per-XCD queues in
+either bin order, then the finishing launches of every bin) gives the same
+bytes as the per-bin launches and matches the oracle: single graphs, expand
+mode, forced overflow, dense-accumulator columns and the batched form."""
 import numpy as np
 import pytest
 
@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 PERSIST = 1 << 28
+LIGHT_FIRST = 1 << 29
 
 
 @pytest.fixture(scope="module")
@@ -41,6 +42,9 @@ def test_persistent_iterate_and_expand_match_per_bin_launches_and_oracle(mcl):
     assert max(st1["bin_cols"][:7]) > 0 and st1["bin_cols"][6] > 0
     same(G, ref)
     assert c1 == c0
+    G2, c2, _ = mcl.iterate(dA, bin_policy=PERSIST | LIGHT_FIRST)  # the other queue order
+    same(G2, ref)
+    assert c2 == c0
     assert st1["nnz_product"] == st0["nnz_product"] and st1["n_selected"] == st0["n_selected"]
     E0, _ = mcl.expand(dA, dA)
     E1, _ = mcl.expand(dA, dA, bin_policy=PERSIST)
