@@ -423,17 +423,19 @@ void use_sliced_source(Mem &mem, mcl::NumericArgs &a, uint32_t policy)
     double *vo = mem.ws<double>(nz + 1);
     uint32_t *rec = mem.ws<uint32_t>(3 * (nz + 1));
     int32_t *go = mem.ws<int32_t>(a.A.ncols * (mcl::SLICE_GROUPS + 1));
+    uint32_t *po = mem.ws<uint32_t>(a.A.ncols * (mcl::SLICE_GROUPS / 4) + 1);
     HIPC(hipMemsetAsync(ro + nz, 0xFF, sizeof(int32_t), mem.st));
     HIPC(hipMemsetAsync(vo + nz, 0, sizeof(double), mem.st));
     HIPC(hipMemsetAsync(rec + 3 * nz, 0xFF, sizeof(uint32_t), mem.st));
     HIPC(hipMemsetAsync(rec + 3 * nz + 1, 0, 2 * sizeof(uint32_t), mem.st));
-    mcl::launch_slice_layout(a.A, ro, vo, rec, go, mem.st);
+    mcl::launch_slice_layout(a.A, ro, vo, rec, go, po, mem.st);
     // every kernel reads the sliced copy (same columns, rows grouped by hash):
     // the sliced-table kernels as packed records, the others as arrays
     a.A.rowidx = ro;
     a.A.val = vo;
     a.srec = rec;
     a.goff = go;
+    a.poff = po;
     a.src_end = (uint32_t)nz;
 }
 

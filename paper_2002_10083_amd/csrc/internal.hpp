@@ -42,6 +42,8 @@ struct NumericArgs {
     PruneArgs pa;
     const void *dummy;        // >= 16 bytes of readable device memory (masked-off loads)
     const int32_t *goff;      // sliced layout of A: SLICE_GROUPS + 1 boundaries per column (or null)
+    const uint32_t *poff;     // sliced layout of A: record index of every fourth group boundary,
+                              //   SLICE_GROUPS / 4 per column, then the record count (or null)
     const uint32_t *srec;     // sliced copy of A (column ranges of A.colptr) as packed 12-byte
                               //   records {row, value low word, value high word}
     uint32_t src_end;         // sliced copy: index of the record past the last (row -1, value 0)
@@ -93,7 +95,7 @@ void launch_phase_plan(int64_t n, const int32_t *bin, const int64_t *base, int64
 // sliced copy of A: rows and values, each column ordered by row group, as separate arrays and
 // as packed 12-byte records (same order), + group boundaries
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, uint32_t *reco, int32_t *goff,
-                         hipStream_t st);
+                         uint32_t *poff, hipStream_t st);
 // Cohen keys per row are stored with this stride (r rounded up to 4)
 inline int cohen_stride(int r) { return (r + 3) & ~3; }
 // Column records of A for the symbolic pass: RP key minima (RP = padded key

@@ -1435,7 +1435,7 @@ typedef uint32_t rec3 __attribute__((ext_vector_type(3), aligned(4)));
 // specified (every consumer treats a run as a set of distinct rows).
 __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restrict__ rowo,
                                                       double *__restrict__ valo, uint32_t *__restrict__ reco,
-                                                      int32_t *__restrict__ goff)
+                                                      int32_t *__restrict__ goff, uint32_t *__restrict__ poff)
 {
     __shared__ int32_t ctr[4][NG];
     const int w = threadIdx.x / WAVE;
@@ -1452,6 +1452,10 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
     const int cur = wave_incl_scan(cnt) - cnt;  // lane g: first position of group g
     goff[k * (NG + 1) + lane()] = cur;
     if (lane() == 0) goff[k * (NG + 1) + NG] = len;
+    // every fourth boundary as an absolute record index (the end of the last
+    // column's last run is the record count)
+    if ((lane() & 3) == 0) poff[k * (NG / 4) + lane() / 4] = (uint32_t)(p0 + cur);
+    if (lane() == 0 && k + 1 == A.ncols) poff[(k + 1) * (NG / 4)] = (uint32_t)(p0 + len);
     group_sync<WAVE>();
     c[lane()] = cur;
     group_sync<WAVE>();
@@ -1468,11 +1472,11 @@ __global__ __launch_bounds__(256) void k_slice_layout(DevCSC A, int32_t *__restr
 }
 
 void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, uint32_t *reco, int32_t *goff,
-                         hipStream_t st)
+                         uint32_t *poff, hipStream_t st)
 {
     if (A.ncols <= 0) return;
     hipLaunchKernelGGL(k_slice_layout, dim3((unsigned)((A.ncols + 3) / 4)), dim3(256), 0, st, A, rowo, valo,
-                       reco, goff);
+                       reco, goff, poff);
 }
 
 // One wave accumulates the row groups [g0, g1) of column j into its private
@@ -1525,14 +1529,23 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             b = a.B.val[bs + t];
         }
     };
+    // a run that starts and ends on a fourth group boundary: both ends from
+    // one 64-byte block of poff (no colptr or goff line per step)
+    const bool q4 = a.poff && ((g0 | g1) & 3) == 0;
     auto run_of = [&](int k, uint32_t &ws, int &len) {
         ws = 0;
         len = 0;
         if (k >= 0) {
-            const int32_t *go = a.goff + (int64_t)k * (NG + 1);
-            const int r0 = go[g0], r1 = go[g1];
-            ws = (uint32_t)a.A.colptr[k] + (uint32_t)r0;  // the sliced copy has fewer than 2^32 entries
-            len = r1 - r0;
+            if (q4) {
+                const uint32_t *po = a.poff + (int64_t)k * (NG / 4);
+                ws = po[g0 >> 2];
+                len = (int)(po[g1 >> 2] - ws);
+            } else {
+                const int32_t *go = a.goff + (int64_t)k * (NG + 1);
+                const int r0 = go[g0], r1 = go[g1];
+                ws = (uint32_t)a.A.colptr[k] + (uint32_t)r0;  // the sliced copy has fewer than 2^32 entries
+                len = r1 - r0;
+            }
         }
     };
     int kn, lenn;
