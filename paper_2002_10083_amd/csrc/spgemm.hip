@@ -1493,7 +1493,10 @@ void launch_slice_layout(const DevCSC &A, int32_t *rowo, double *valo, uint32_t 
 // waves, which own disjoint rows, cleared by the caller) and marks the row
 // in the bitmap dbits; wkey, wovf, col_keys and the capacities are unused
 // and the return value is 0.
-template <int SW, int MODE, int D, bool DENSE = false>
+// NARROW: the sliced copy holds fewer than 2^32 bytes (NARROW_RECS records),
+// so a record's address is a 32-bit byte offset, advanced by adds only.
+constexpr uint32_t NARROW_RECS = 0xFFFFFFFFu / 12u;
+template <int SW, int MODE, int D, bool DENSE = false, bool NARROW = false>
 __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1, int32_t *wkey, double *wval,
                                 int *wovf, int capw, double *never, int *col_keys, int64_t col_cap,
                                 int32_t dlo = 0, uint32_t *dbits = nullptr)
@@ -1515,6 +1518,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
     int published = 0;  // of which already added to *col_keys
     int lovf = 0;       // a probe of this lane failed
     int sinkh = 0;      // high words of the products a lane saw (kept live, never used)
+    const uint32_t lane12 = 12u * (uint32_t)lane();
 
     // Step metadata of a batch of 64 steps (lane l: step tb + l): the row k
     // and value of b, then this wave's run in A_*k (start, length).  The next
@@ -1579,6 +1583,8 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         // lane l's run as an offset into A: entry f of the packed sequence,
         // f in [pre_l, pre_l + len_l), is A entry f + base_l
         const uint32_t basev = ws - (uint32_t)pre;  // modulo 2^32
+        // NARROW: the same in bytes (12 * entry index, exact below 2^32)
+        const uint32_t baseb = NARROW ? basev * 12u : 0u;
         auto issue = [&](Grp &G, int c0) {
             // two sweeps: the lane permutes of all D chunks first (one wait
             // for all of them), then the addresses and the loads
@@ -1592,10 +1598,14 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 // step is the last run starting at or before its entry
                 const int cnt0 = __popcll(ballot(pre <= F));
                 const int k = __popcll(ballot(pre > F && pre < F + WAVE));
+                // (the first four steps unrolled: a chunk rarely holds more)
                 int rank = 0;
-                for (int q = 0; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < k) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
+                for (int q = 4; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
                 const int u = cnt0 - 1 + rank;
-                bu[i] = (uint32_t)shfl_i((int)basev, u);
+                bu[i] = (uint32_t)shfl_i((int)(NARROW ? baseb : basev), u);
                 if (MODE != MODE_COUNT) G.bb[i] = shfl_d(bv, u);
                 G.sub[i] = rank;  // position of the lane's step among the chunk's steps
                 G.nsub[i] = k + 1;
@@ -1604,10 +1614,28 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             for (int i = 0; i < D; ++i) {
                 const int F = (c0 + i) * WAVE;
                 // past the run ends: the sentinel entry (row -1, value 0)
-                const uint32_t ad = (F + lane() < total) ? bu[i] + (uint32_t)(F + lane()) : a.src_end;
-                const rec3 x = ldg((const rec3 *)(a.srec + (uint64_t)ad * 3));
+                rec3 x;
+                if constexpr (NARROW) {
+                    const uint32_t ab = (F + lane() < total) ? bu[i] + 12u * (uint32_t)F + lane12 : a.src_end * 12u;
+                    x = ldg((const rec3 *)((const char *)a.srec + ab));
+                } else {
+                    const uint32_t ad = (F + lane() < total) ? bu[i] + (uint32_t)(F + lane()) : a.src_end;
+                    x = ldg((const rec3 *)(a.srec + (uint64_t)ad * 3));
+                }
                 G.rr[i] = (int32_t)x.x;
                 if (MODE != MODE_COUNT) G.vv[i] = __longlong_as_double((int64_t)(((uint64_t)x.z << 32) | x.y));
+            }
+        };
+        // the adds of one chunk, step by step (sub = the lane's step among
+        // the chunk's nsub steps; the first four unrolled)
+        auto ordered_adds = [&](int sub, int nsub, int slot, double x) {
+            const int s2 = slot >= 0 ? sub : -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (s2 == q) lds_atomic_add(wval + slot, x);
+            if (nsub > 4) {
+                for (int q = 4; q < nsub; ++q)
+                    if (s2 == q) lds_atomic_add(wval + slot, x);
             }
         };
         auto fold_dense = [&](Grp &G) {
@@ -1623,9 +1651,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 if (sl[i] >= 0 && prod[i] == 0.0) atomicOr(&dbits[sl[i] >> 5], 1u << (sl[i] & 31));
             }
 #pragma unroll
-            for (int i = 0; i < D; ++i)
-                for (int q = 0; q < G.nsub[i]; ++q)
-                    if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod[i]);
+            for (int i = 0; i < D; ++i) ordered_adds(G.sub[i], G.nsub[i], sl[i], prod[i]);
         };
         auto fold_hash = [&](Grp &G) {
             uint32_t hb[D];
@@ -1658,9 +1684,7 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                     sinkh |= __double2hiint(prod[i]);  // keeps the value load out of the branch
                 }
 #pragma unroll
-                for (int i = 0; i < D; ++i)
-                    for (int q = 0; q < G.nsub[i]; ++q)
-                        if (G.sub[i] == q && sl[i] >= 0) lds_atomic_add(wval + sl[i], prod[i]);
+                for (int i = 0; i < D; ++i) ordered_adds(G.sub[i], G.nsub[i], sl[i], prod[i]);
             }
             const int delta = __builtin_amdgcn_readfirstlane(keys_w - published);
             if (delta != 0) {  // new keys: publish them (no return value to wait for)
@@ -1733,7 +1757,10 @@ __global__ __launch_bounds__(NW * WAVE) void k_numeric_hsplit(NumericArgs a)
     if (tid == 0) sh.misc[8] = 0;
     __syncthreads();
     const int64_t col_cap = a.capv ? min((int64_t)CAPT, a.capv[j]) : (int64_t)CAPT;
-    const int keys_w = slice_accumulate<SW, MODE, D>(a, j, w * G, (w + 1) * G, sh.key + w * SW, sh.val + w * SW,
+    const int keys_w = a.src_end <= NARROW_RECS
+        ? slice_accumulate<SW, MODE, D, false, true>(a, j, w * G, (w + 1) * G, sh.key + w * SW, sh.val + w * SW,
+                                                     &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[8], col_cap)
+        : slice_accumulate<SW, MODE, D>(a, j, w * G, (w + 1) * G, sh.key + w * SW, sh.val + w * SW,
                                                      &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[8], col_cap);
     if (lane() == 0) {
         sh.wcnt[w] = keys_w;
@@ -1844,7 +1871,10 @@ __device__ __forceinline__ void numeric_part_body(const NumericArgs &a)
     __syncthreads();
     const int64_t col_cap = a.capv ? a.capv[j] : (int64_t)(P * NWP * CAPW);
     const int g0 = p * (NG / P) + w * G;
-    const int keys_w = slice_accumulate<SW, MODE, D>(a, j, g0, g0 + G, sh.key + w * SW, sh.val + w * SW,
+    const int keys_w = a.src_end <= NARROW_RECS
+        ? slice_accumulate<SW, MODE, D, false, true>(a, j, g0, g0 + G, sh.key + w * SW, sh.val + w * SW,
+                                                     &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[0], col_cap)
+        : slice_accumulate<SW, MODE, D>(a, j, g0, g0 + G, sh.key + w * SW, sh.val + w * SW,
                                                      &sh.wovf[w], CAPW, &sh.dmisc[3], &sh.misc[0], col_cap);
     if (lane() == 0) {
         sh.wcnt[w] = keys_w;
@@ -2075,7 +2105,10 @@ __device__ __forceinline__ void part_wave(const NumericArgs &a, int64_t j, int p
     const int64_t col_cap = a.capv[j];
     if (lane() == 0) wmisc[0] = 0;  // keys of the column placed by this wave
     group_sync<WAVE>();
-    const int keys_w = slice_accumulate<SW, MODE, 2>(a, j, p * G, p * G + G, wkey, wval, &wmisc[1], CAPW, wdm,
+    const int keys_w = a.src_end <= NARROW_RECS
+        ? slice_accumulate<SW, MODE, 2, false, true>(a, j, p * G, p * G + G, wkey, wval, &wmisc[1], CAPW, wdm,
+                                                     &wmisc[0], col_cap)
+        : slice_accumulate<SW, MODE, 2>(a, j, p * G, p * G + G, wkey, wval, &wmisc[1], CAPW, wdm,
                                                      &wmisc[0], col_cap);
     // as in the split kernels: a complete key count is added to the
     // column's counter even when the column overflows
