@@ -1058,19 +1058,24 @@ __device__ void sort_table(const int32_t *tkey, int S, int m, int32_t lo, int64_
 // sc.sorted: prune (Alg. 1), inflation with column re-normalisation, the
 // change against the previous iterate (column j of B, which is A), and the
 // per-column outputs.  find(row) returns the slot of a row or -1.
+// fixed_mode >= 0: the prune branch and threshold were decided by the
+// caller (fixed_mode, fixed_t) and the m listed keys are the column's kept
+// entries; m_prod >= 0 is then the column's unpruned entry count.
 template <int NT, bool GS, typename IdxT, typename Find, typename Keys = const int32_t *>
 __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t bs, int mj,
                                  int64_t base, Keys tkey, double *tval,
-                                 const Scratch<IdxT> &sc, Find find)
+                                 const Scratch<IdxT> &sc, Find find, int m_prod = -1, int fixed_mode = -1,
+                                 double fixed_t = 0.0)
 {
     const int tid = threadIdx.x % NT;
     const int w = tid / WAVE;
     constexpr int NWV = (NT + WAVE - 1) / WAVE;
     // ---------------- prune (Alg. 1) ----------------
     auto getv = [&](int p) { return tval[sc.sorted[p]]; };
-    int pmode;
-    double t;
-    prune_decide<NT, GS>(getv, m, a.pa, sc.p0, sc.p1, sc.ip, sc.hist, sc.misc, sc.dmisc, &pmode, &t);
+    int pmode = fixed_mode;
+    double t = fixed_t;
+    if (fixed_mode < 0)
+        prune_decide<NT, GS>(getv, m, a.pa, sc.p0, sc.p1, sc.ip, sc.hist, sc.misc, sc.dmisc, &pmode, &t);
 
     // kept entries, in row order, into sc.list
     const int nblk = (m + WAVE - 1) / WAVE;
@@ -1146,7 +1151,7 @@ __device__ void iterate_epilogue(const NumericArgs &a, int64_t j, int m, int64_t
     }
     if (tid == 0) {
         a.out_cnt[j] = K;
-        if (a.nnz_prod) a.nnz_prod[j] = m;
+        if (a.nnz_prod) a.nnz_prod[j] = m_prod >= 0 ? m_prod : m;
         if (a.delta) a.delta[j] = dmax;
         if (a.mode) a.mode[j] = (int8_t)pmode;
     }
@@ -2019,22 +2024,69 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
         if (tid == 0) a.out_cnt[j] = m;
         return;
     }
-    sort_table<NT, false, uint16_t>(sh.key, m, m, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
-                                    [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
-    __syncthreads();
     Scratch<uint16_t> sc{sh.key, sh.val, sh.list, sh.sorted, sh.bcnt, sh.bcur, sh.p0, sh.p1,
                          sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
-    iterate_epilogue<NT, false, uint16_t>(a, j, m, bs, mj, base, sh.key, sh.val, sc, [&](int32_t k) {
-        int l = 0, h = m;  // first rank with key >= k
-        while (l < h) {
-            const int mid = (l + h) >> 1;
-            if (sh.key[sh.sorted[mid]] < k) l = mid + 1;
-            else h = mid;
+    constexpr int NWV = NT / WAVE;
+    const int w = tid / WAVE;
+    const int nblk = (m + WAVE - 1) / WAVE;
+    // nP: entries >= theta (order-independent)
+    int cnt = 0;
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        cnt += __popcll(ballot(p < m && sh.val[p] >= a.pa.theta));
+    }
+    if (lane() == 0) sh.wsum[w] = cnt;
+    __syncthreads();
+    int nP = 0;
+    for (int q = 0; q < NWV; ++q) nP += sh.wsum[q];
+    __syncthreads();
+    int msort = m;  // entries taking part in the sort and the epilogue
+    int fmode = -1;
+    double ft = 0.0;
+    if (a.pa.R <= 0 || nP >= a.pa.R) {
+        // The recovery branch cannot apply, so the column sums (which only
+        // decide it) are not needed: take the branch and threshold from
+        // nP and an order-independent selection over the unsorted entries,
+        // drop the entries below the threshold (their keys become empty)
+        // and sort only the kept ones.  Same kept set, order and values as
+        // deciding on the whole sorted column.
+        fmode = 0;
+        ft = a.pa.theta;
+        if (a.pa.S > 0 && nP > a.pa.S) {
+            fmode = 2;
+            ft = radix_kth_largest<NT, false>([&](int p) { return sh.val[p]; }, m, a.pa.S, sh.hist, sh.misc,
+                                              sh.dmisc);
         }
-        return (l < m && sh.key[sh.sorted[l]] == k) ? (int)sh.sorted[l] : -1;
-    });
+        int kc = 0;
+        for (int b = w; b < nblk; b += NWV) {
+            const int p = b * WAVE + lane();
+            const bool keep = p < m && sh.val[p] >= ft;
+            if (p < m && !keep) sh.key[p] = EMPTY_KEY;
+            kc += __popcll(ballot(keep));
+        }
+        if (lane() == 0) sh.wsum[w] = kc;
+        __syncthreads();
+        msort = 0;
+        for (int q = 0; q < NWV; ++q) msort += sh.wsum[q];
+        __syncthreads();
+    }
+    sort_table<NT, false, uint16_t>(sh.key, m, msort, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
+                                    [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
+    __syncthreads();
+    iterate_epilogue<NT, false, uint16_t>(
+        a, j, msort, bs, mj, base, sh.key, sh.val, sc,
+        [&](int32_t k) {
+            int l = 0, h = msort;  // first rank with key >= k
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (sh.key[sh.sorted[mid]] < k) l = mid + 1;
+                else h = mid;
+            }
+            return (l < msort && sh.key[sh.sorted[l]] == k) ? (int)sh.sorted[l] : -1;
+        },
+        m, fmode, ft);
 }
 
 // Finishing launches of a split bin whose columns hold at most `mmax` <=
