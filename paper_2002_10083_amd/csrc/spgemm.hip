@@ -1965,6 +1965,59 @@ __global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) vo
     numeric_part_body<NWP, SW, P, MODE, D>(a);
 }
 
+// Prune decision before the sort, for an unsorted column of m entries
+// (key[p], val[p]).  When the recovery branch cannot apply (R = 0 or at least
+// R entries >= theta), the column sums, which only decide that branch, are
+// not needed: the branch and threshold follow from nP and an
+// order-independent selection over the unsorted values, the entries below
+// the threshold are dropped (their keys become EMPTY_KEY) and only the kept
+// ones need sorting -- the same kept set, order and values as deciding on
+// the whole sorted column.  Returns the number of entries left to sort (m
+// when the recovery branch may apply; fmode = -1 then, else the branch and
+// ft the threshold).  Called by all NT threads of the group.
+template <int NT, bool GS, typename KeyT>
+__device__ int select_first(const NumericArgs &a, int m, KeyT *key, const double *val, int *wsum, int *hist,
+                            int *misc, double *dmisc, int &fmode, double &ft)
+{
+    constexpr int NWV = NT / WAVE;
+    static_assert(NT % WAVE == 0, "whole waves");
+    const int tid = threadIdx.x % NT;
+    const int w = tid / WAVE;
+    const int nblk = (m + WAVE - 1) / WAVE;
+    int cnt = 0;  // nP: entries >= theta
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        cnt += __popcll(ballot(p < m && val[p] >= a.pa.theta));
+    }
+    if (lane() == 0) wsum[w] = cnt;
+    group_sync<NT, GS>();
+    int nP = 0;
+    for (int q = 0; q < NWV; ++q) nP += wsum[q];
+    group_sync<NT, GS>();
+    fmode = -1;
+    ft = 0.0;
+    if (!(a.pa.R <= 0 || nP >= a.pa.R)) return m;
+    fmode = 0;
+    ft = a.pa.theta;
+    if (a.pa.S > 0 && nP > a.pa.S) {
+        fmode = 2;
+        ft = radix_kth_largest<NT, GS>([&](int p) { return val[p]; }, m, a.pa.S, hist, misc, dmisc);
+    }
+    int kc = 0;
+    for (int b = w; b < nblk; b += NWV) {
+        const int p = b * WAVE + lane();
+        const bool keep = p < m && val[p] >= ft;
+        if (p < m && !keep) key[p] = EMPTY_KEY;
+        kc += __popcll(ballot(keep));
+    }
+    if (lane() == 0) wsum[w] = kc;
+    group_sync<NT, GS>();
+    int msort = 0;
+    for (int q = 0; q < NWV; ++q) msort += wsum[q];
+    group_sync<NT, GS>();
+    return msort;
+}
+
 // Finishing kernel of the split sliced tables: one workgroup per column
 // loads the m appended entries into LDS, sorts them by row and writes them
 // (expand) or runs the fused epilogue (iterate).  Several launches of
@@ -2028,50 +2081,9 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
                          sh.ip, sh.hist, sh.misc, sh.dmisc, sh.wsum};
     const int64_t bs = a.B.colptr[j];
     const int mj = (int)(a.B.colptr[j + 1] - bs);
-    constexpr int NWV = NT / WAVE;
-    const int w = tid / WAVE;
-    const int nblk = (m + WAVE - 1) / WAVE;
-    // nP: entries >= theta (order-independent)
-    int cnt = 0;
-    for (int b = w; b < nblk; b += NWV) {
-        const int p = b * WAVE + lane();
-        cnt += __popcll(ballot(p < m && sh.val[p] >= a.pa.theta));
-    }
-    if (lane() == 0) sh.wsum[w] = cnt;
-    __syncthreads();
-    int nP = 0;
-    for (int q = 0; q < NWV; ++q) nP += sh.wsum[q];
-    __syncthreads();
-    int msort = m;  // entries taking part in the sort and the epilogue
-    int fmode = -1;
-    double ft = 0.0;
-    if (a.pa.R <= 0 || nP >= a.pa.R) {
-        // The recovery branch cannot apply, so the column sums (which only
-        // decide it) are not needed: take the branch and threshold from
-        // nP and an order-independent selection over the unsorted entries,
-        // drop the entries below the threshold (their keys become empty)
-        // and sort only the kept ones.  Same kept set, order and values as
-        // deciding on the whole sorted column.
-        fmode = 0;
-        ft = a.pa.theta;
-        if (a.pa.S > 0 && nP > a.pa.S) {
-            fmode = 2;
-            ft = radix_kth_largest<NT, false>([&](int p) { return sh.val[p]; }, m, a.pa.S, sh.hist, sh.misc,
-                                              sh.dmisc);
-        }
-        int kc = 0;
-        for (int b = w; b < nblk; b += NWV) {
-            const int p = b * WAVE + lane();
-            const bool keep = p < m && sh.val[p] >= ft;
-            if (p < m && !keep) sh.key[p] = EMPTY_KEY;
-            kc += __popcll(ballot(keep));
-        }
-        if (lane() == 0) sh.wsum[w] = kc;
-        __syncthreads();
-        msort = 0;
-        for (int q = 0; q < NWV; ++q) msort += sh.wsum[q];
-        __syncthreads();
-    }
+    int fmode;
+    double ft;
+    const int msort = select_first<NT, false>(a, m, sh.key, sh.val, sh.wsum, sh.hist, sh.misc, sh.dmisc, fmode, ft);
     sort_table<NT, false, uint16_t>(sh.key, m, msort, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
                                     [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
     __syncthreads();
@@ -2565,20 +2577,26 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
             });
             if (tid == 0) a.out_cnt[j] = m;
         } else {
-            sort_table<NT, true, int32_t>(skey, m, m, lo, span, bcnt, bcur, NB, list, wsum,
+            int fmode;
+            double ft;
+            const int msort = select_first<NT, true>(a, m, skey, sval, wsum, hist, misc, dmisc, fmode, ft);
+            sort_table<NT, true, int32_t>(skey, m, msort, lo, span, bcnt, bcur, NB, list, wsum,
                                           [&](int rank, int s) { sorted[rank] = s; });
             __syncthreads();
             const int64_t bs = a.B.colptr[j];
             const int mj = (int)(a.B.colptr[j + 1] - bs);
-            iterate_epilogue<NT, true, int32_t>(a, j, m, bs, mj, base, skey, sval, sc, [&](int32_t k) {
-                int l = 0, h = m;  // first rank with key >= k
-                while (l < h) {
-                    const int mid = (l + h) >> 1;
-                    if (skey[sorted[mid]] < k) l = mid + 1;
-                    else h = mid;
-                }
-                return (l < m && skey[sorted[l]] == k) ? sorted[l] : -1;
-            });
+            iterate_epilogue<NT, true, int32_t>(
+                a, j, msort, bs, mj, base, skey, sval, sc,
+                [&](int32_t k) {
+                    int l = 0, h = msort;  // first rank with key >= k
+                    while (l < h) {
+                        const int mid = (l + h) >> 1;
+                        if (skey[sorted[mid]] < k) l = mid + 1;
+                        else h = mid;
+                    }
+                    return (l < msort && skey[sorted[l]] == k) ? sorted[l] : -1;
+                },
+                m, fmode, ft);
         }
         __syncthreads();
     }
