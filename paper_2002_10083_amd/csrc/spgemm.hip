@@ -1966,18 +1966,23 @@ __global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) vo
 }
 
 // Prune decision before the sort, for an unsorted column of m entries
-// (key[p], val[p]).  When the recovery branch cannot apply (R = 0 or at least
-// R entries >= theta), the column sums, which only decide that branch, are
-// not needed: the branch and threshold follow from nP and an
-// order-independent selection over the unsorted values, the entries below
-// the threshold are dropped (their keys become EMPTY_KEY) and only the kept
-// ones need sorting -- the same kept set, order and values as deciding on
-// the whole sorted column.  Returns the number of entries left to sort (m
-// when the recovery branch may apply; fmode = -1 then, else the branch and
-// ft the threshold).  Called by all NT threads of the group.
+// (key[p], val[p]).  The column sums mB and mP (of all entries and of those
+// >= theta) only decide the recovery branch (nP < R and mP < pct * mB); the
+// fused epilogue forms them by a fixed tree over the sorted column.  Here
+// they are summed in the unsorted order instead: both sums of m values in
+// [0, 1] lie within m * 2^-53 * mB of the exact ones (whatever the order),
+// so when |mP - pct * mB| exceeds 4 * m * 2^-53 * max(1, pct) * mB the
+// branch is the one the sorted sums would take.  The branch and threshold then follow from nP and
+// an order-independent selection over the unsorted values, the entries
+// below the threshold are dropped (their keys become EMPTY_KEY) and only the
+// kept ones need sorting -- the same kept set, order and values as deciding
+// on the whole sorted column.  Returns the number of entries left to sort
+// (m, with fmode = -1, when the margin is too small to decide; else fmode
+// is the branch and ft the threshold).  Called by all NT threads of the
+// group.
 template <int NT, bool GS, typename KeyT>
-__device__ int select_first(const NumericArgs &a, int m, KeyT *key, const double *val, int *wsum, int *hist,
-                            int *misc, double *dmisc, int &fmode, double &ft)
+__device__ int select_first(const NumericArgs &a, int m, KeyT *key, const double *val, int *wsum, double *p0,
+                            double *p1, int *hist, int *misc, double *dmisc, int &fmode, double &ft)
 {
     constexpr int NWV = NT / WAVE;
     static_assert(NT % WAVE == 0, "whole waves");
@@ -1996,12 +2001,40 @@ __device__ int select_first(const NumericArgs &a, int m, KeyT *key, const double
     group_sync<NT, GS>();
     fmode = -1;
     ft = 0.0;
-    if (!(a.pa.R <= 0 || nP >= a.pa.R)) return m;
-    fmode = 0;
-    ft = a.pa.theta;
-    if (a.pa.S > 0 && nP > a.pa.S) {
+    bool rec = false;
+    if (a.pa.R > 0 && nP < a.pa.R) {
+        double sb = 0.0, sp = 0.0;
+        for (int b = w; b < nblk; b += NWV) {
+            const int p = b * WAVE + lane();
+            const double v = p < m ? val[p] : 0.0;
+            sb += wave_sum(v);
+            sp += wave_sum(v >= a.pa.theta ? v : 0.0);
+        }
+        if (lane() == 0) {  // per-wave partial sums (p0, p1 hold at least NWV entries)
+            p0[w] = sb;
+            p1[w] = sp;
+        }
+        group_sync<NT, GS>();
+        double mB = 0.0, mP = 0.0;
+        for (int q = 0; q < NWV; ++q) {
+            mB += p0[q];
+            mP += p1[q];
+        }
+        group_sync<NT, GS>();
+        const double d = mP - a.pa.pct * mB;
+        if (!(fabs(d) > 4.0 * (double)m * 0x1p-53 * fmax(1.0, a.pa.pct) * mB)) return m;  // too close to call
+        rec = d < 0.0;
+    }
+    if (rec) {
+        fmode = 1;
+        ft = (m >= a.pa.R) ? radix_kth_largest<NT, GS>([&](int p) { return val[p]; }, m, a.pa.R, hist, misc, dmisc)
+                           : 0.0;
+    } else if (a.pa.S > 0 && nP > a.pa.S) {
         fmode = 2;
         ft = radix_kth_largest<NT, GS>([&](int p) { return val[p]; }, m, a.pa.S, hist, misc, dmisc);
+    } else {
+        fmode = 0;
+        ft = a.pa.theta;
     }
     int kc = 0;
     for (int b = w; b < nblk; b += NWV) {
@@ -2031,6 +2064,7 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
 {
     constexpr int NBS = CAPF / 3;  // sort buckets
     constexpr int NBLK = CAPF / WAVE + 2;
+    static_assert(NBLK >= NT / WAVE, "per-wave partial sums fit p0 and p1");
     struct alignas(16) Sh {
         double val[CAPF];
         int32_t key[CAPF];
@@ -2083,7 +2117,8 @@ __global__ __launch_bounds__(NT) void k_finish_part(NumericArgs a, int mlo, int 
     const int mj = (int)(a.B.colptr[j + 1] - bs);
     int fmode;
     double ft;
-    const int msort = select_first<NT, false>(a, m, sh.key, sh.val, sh.wsum, sh.hist, sh.misc, sh.dmisc, fmode, ft);
+    const int msort = select_first<NT, false>(a, m, sh.key, sh.val, sh.wsum, sh.p0, sh.p1, sh.hist, sh.misc, sh.dmisc,
+                                                fmode, ft);
     sort_table<NT, false, uint16_t>(sh.key, m, msort, lo, span, sh.bcnt, sh.bcur, NBS, sh.list, sh.wsum,
                                     [&](int rank, int s) { sh.sorted[rank] = (uint16_t)s; });
     __syncthreads();
@@ -2579,7 +2614,7 @@ __global__ __launch_bounds__(1024) void k_finish_mpass(NumericArgs a, char *slab
         } else {
             int fmode;
             double ft;
-            const int msort = select_first<NT, true>(a, m, skey, sval, wsum, hist, misc, dmisc, fmode, ft);
+            const int msort = select_first<NT, true>(a, m, skey, sval, wsum, p0, p1, hist, misc, dmisc, fmode, ft);
             sort_table<NT, true, int32_t>(skey, m, msort, lo, span, bcnt, bcur, NB, list, wsum,
                                           [&](int rank, int s) { sorted[rank] = s; });
             __syncthreads();
