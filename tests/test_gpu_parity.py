@@ -216,6 +216,20 @@ def test_launch_variants_are_bit_identical(mcl):
         assert torch.equal(E1.rowidx, E0.rowidx) and torch.equal(E1.val, E0.val)
 
 
+@pytest.mark.parametrize("S,R,theta", [(40, 60, 1e-3), (20, 0, 5e-3), (0, 100, 1e-2), (300, 2500, 2e-3)])
+def test_iterate_parity_split_bins_prune_branches(mcl, S, R, theta):
+    """Columns of the split bins (4-6) and of the multi-pass bin decide their
+    prune branch before sorting (selection, threshold, and recovery decided
+    from the unsorted column sums); every branch must match the oracle."""
+    A = oracle.normalize(planted_graph(40000, 2000, s_cap=2100, seed=73))
+    _, _, st = check_iterate(mcl, A, theta=theta, S=S, R=R)
+    assert max(st["bin_cols"][4:7]) > 0
+    if R > 0:
+        assert st["n_recovered"] > 0
+    if S > 0:
+        assert st["n_selected"] > 0
+
+
 def test_iterate_parity_big_clusters(mcl):
     A = oracle.normalize(planted_graph(40000, 2000, s_cap=2100, seed=72))
     _, _, st = check_iterate(mcl, A)
