@@ -574,6 +574,8 @@ def main():
     ap.add_argument("--estimator", default="cohen", choices=["cohen", "bound"])
     ap.add_argument("--policy", type=lambda x: int(x, 0), default=None,
                     help="bin launch policy (default: tuned table if present)")
+    ap.add_argument("--est-scale", type=float, default=None,
+                    help="table sizing margin (default: the tuned one)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--loop-sample", type=int, default=0,
@@ -617,6 +619,8 @@ def main():
     policy, scale, keys = tuning.load_policy("iterate")
     if args.policy is not None:
         policy = args.policy
+    if args.est_scale is not None:
+        scale = args.est_scale
     params = mcl.default_params(estimator=est, bin_policy=policy, est_scale=scale, cohen_keys=keys)
 
     if args.calibrate_copy:
