@@ -1557,11 +1557,34 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             }
         }
     };
+    // The non-empty runs of a batch move to the low lanes, in step order
+    // (forward permute; the lanes above the last non-empty run become
+    // empty), so the run starts of a batch are strictly increasing and no
+    // two steps start at one position.
+    auto compact = [&](uint32_t &ws, int &len, double &bv) {
+        const uint64_t ne = ballot(len > 0);
+        if (ne == ~0ull) return;
+        const int dst = (len > 0 ? popc_below(ne) : WAVE - 1) << 2;
+        ws = (uint32_t)__builtin_amdgcn_ds_permute(dst, (int)ws);
+        len = __builtin_amdgcn_ds_permute(dst, len);
+        if (MODE != MODE_COUNT) {
+            const int64_t bb = __double_as_longlong(bv);
+            const int lo = __builtin_amdgcn_ds_permute(dst, (int)(uint32_t)bb);
+            const int hi = __builtin_amdgcn_ds_permute(dst, (int)(bb >> 32));
+            bv = __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+        }
+        if (lane() >= __popcll(ne)) {
+            ws = 0;
+            len = 0;
+            bv = 0.0;
+        }
+    };
     int kn, lenn;
     uint32_t wsn;
     double bvn;
     step_of(0, kn, bvn);
     run_of(kn, wsn, lenn);
+    compact(wsn, lenn, bvn);
     for (int tb = 0; tb < mj && !overflow; tb += WAVE) {
         const uint32_t ws = wsn;
         const int len = lenn;
@@ -1601,14 +1624,16 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 // [0, cnt0) start at or before F (cnt0 >= 1: lane 0 starts
                 // at 0), the next k lanes start inside the chunk; a lane's
                 // step is the last run starting at or before its entry
+                // The runs starting inside the chunk mark their first entry
+                // (forward permute of a 1 to lane pre - F; lanes nobody
+                // writes read 0); a lane's rank among the chunk's steps is
+                // the number of marks at or below it.
                 const int cnt0 = __popcll(ballot(pre <= F));
-                const int k = __popcll(ballot(pre > F && pre < F + WAVE));
-                // (the first four steps unrolled: a chunk rarely holds more)
-                int rank = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q < k) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
-                for (int q = 4; q < k; ++q) rank += (F + lane() >= readlane_i(pre, cnt0 + q)) ? 1 : 0;
+                const bool starts = len > 0 && pre > F && pre < F + WAVE;
+                const int mark = __builtin_amdgcn_ds_permute(starts ? (pre - F) << 2 : 0, starts ? 1 : 0);
+                const uint64_t M = ballot(mark != 0);
+                const int k = __popcll(M);
+                const int rank = popc_below(M) + mark;
                 const int u = cnt0 - 1 + rank;
                 bu[i] = (uint32_t)shfl_i((int)(NARROW ? baseb : basev), u);
                 if (MODE != MODE_COUNT) G.bb[i] = shfl_d(bv, u);
@@ -1711,13 +1736,17 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
             fold(GA);
             if (next_runs) {
                 run_of(kn, wsn, lenn);
+                compact(wsn, lenn, bvn);
                 next_runs = false;
             }
             if (c0 + D >= nchunk || overflow) break;
             issue(GA, c0 + 2 * D);
             fold(GB);
         }
-        if (next_runs) run_of(kn, wsn, lenn);
+        if (next_runs) {
+            run_of(kn, wsn, lenn);
+            compact(wsn, lenn, bvn);
+        }
     }
     if constexpr (!DENSE) {
         const bool any_ovf = ballot(lovf != 0) != 0;
