@@ -1658,15 +1658,17 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
         };
         // the adds of one chunk, step by step (sub = the lane's step among
         // the chunk's nsub steps; the first four unrolled)
+        // One masked atomic per step, in step order: a row met by two steps
+        // of the chunk sits in two lanes, and only successive instructions
+        // of a wave are documented to apply in order (lanes of one
+        // instruction that share an address are applied in an unspecified
+        // order).  Written as a loop with a run-time trip count, so the
+        // compiler cannot merge the steps' atomics into one instruction --
+        // which it may do with an unrolled form, since every lane runs
+        // exactly one of them.
         auto ordered_adds = [&](int sub, int nsub, int slot, double x) {
-            const int s2 = slot >= 0 ? sub : -1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (s2 == q) lds_atomic_add(wval + slot, x);
-            if (nsub > 4) {
-                for (int q = 4; q < nsub; ++q)
-                    if (s2 == q) lds_atomic_add(wval + slot, x);
-            }
+            for (int q = 0; q < nsub; ++q)
+                if (sub == q && slot >= 0) lds_atomic_add(wval + slot, x);
         };
         auto fold_dense = [&](Grp &G) {
             double prod[D];
