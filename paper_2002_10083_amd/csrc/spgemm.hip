@@ -1656,9 +1656,8 @@ __device__ int slice_accumulate(const NumericArgs &a, int64_t j, int g0, int g1,
                 if (MODE != MODE_COUNT) G.vv[i] = __longlong_as_double((int64_t)(((uint64_t)x.z << 32) | x.y));
             }
         };
-        // the adds of one chunk, step by step (sub = the lane's step among
-        // the chunk's nsub steps; the first four unrolled)
-        // One masked atomic per step, in step order: a row met by two steps
+        // The adds of one chunk (sub = the lane's step among the chunk's
+        // nsub steps).  One masked atomic per step, in step order: a row met by two steps
         // of the chunk sits in two lanes, and only successive instructions
         // of a wave are documented to apply in order (lanes of one
         // instruction that share an address are applied in an unspecified
@@ -2000,14 +1999,14 @@ __global__ __launch_bounds__(NWP * WAVE) __attribute__((amdgpu_num_vgpr(64))) vo
 // (key[p], val[p]).  The column sums mB and mP (of all entries and of those
 // >= theta) only decide the recovery branch (nP < R and mP < pct * mB); the
 // fused epilogue forms them by a fixed tree over the sorted column.  Here
-// they are summed in the unsorted order instead: both sums of m values in
-// [0, 1] lie within m * 2^-53 * mB of the exact ones (whatever the order),
-// so when |mP - pct * mB| exceeds 4 * m * 2^-53 * max(1, pct) * mB the
-// branch is the one the sorted sums would take.  The branch and threshold then follow from nP and
-// an order-independent selection over the unsorted values, the entries
-// below the threshold are dropped (their keys become EMPTY_KEY) and only the
-// kept ones need sorting -- the same kept set, order and values as deciding
-// on the whole sorted column.  Returns the number of entries left to sort
+// they are summed in the unsorted order instead: a sum of m nonnegative
+// values lies within m * 2^-53 times the sum of the exact one, whatever the
+// order, so when |mP - pct * mB| exceeds 4 * m * 2^-53 * max(1, pct) * mB
+// the branch is the one the sorted sums would take.  The branch and
+// threshold then follow from nP and an order-independent selection over
+// the unsorted values, the entries below the threshold are dropped (their
+// keys become EMPTY_KEY) and only the kept ones need sorting -- the same
+// kept set, order and values as deciding on the whole sorted column.  Returns the number of entries left to sort
 // (m, with fmode = -1, when the margin is too small to decide; else fmode
 // is the branch and ft the threshold).  Called by all NT threads of the
 // group.
