@@ -53,8 +53,13 @@ __global__ __launch_bounds__(256) void k_merge_ntiles(const DevCSC *__restrict__
 }
 
 // One wave per column: the column of every tile and the first row of every
-// tile.  Boundary k is found by a binary search over the row value; each
-// probe counts the elements below it in all lists (lanes take the lists).
+// tile.  Boundary k is the smallest row value with at least k * tile
+// elements below it over all lists.  With P <= 32 lists the wave probes G =
+// 64 / PP row values at once (PP = P rounded up to a power of two; lane
+// g * PP + q counts the elements of list q below probe g, a butterfly over
+// the group's PP lanes sums them), so each round cuts the range into G + 1
+// parts instead of 2; with more lists the lanes take the lists and probe
+// one value per round.
 __global__ __launch_bounds__(256) void k_merge_bounds(const DevCSC *__restrict__ parts, int P, int64_t nrows,
                                                       int64_t ncols, int64_t tile,
                                                       const int64_t *__restrict__ tile_ptr,
@@ -68,6 +73,35 @@ __global__ __launch_bounds__(256) void k_merge_bounds(const DevCSC *__restrict__
         for (int k = lane(); k < T; k += WAVE) {
             tile_col[t0 + k] = (int32_t)j;
             if (k == 0) tile_row[t0] = 0;
+        }
+        const int PP = P <= 1 ? 1 : 1 << (32 - __clz(P - 1));
+        if (T > 1 && PP <= WAVE / 2) {
+            const int G = WAVE / PP, g = lane() / PP, q = lane() % PP;
+            int64_t c0 = 0, n = 0;
+            if (q < P) {
+                c0 = parts[q].colptr[j];
+                n = parts[q].colptr[j + 1] - c0;
+            }
+            for (int k = 1; k < T; ++k) {
+                const int64_t target = (int64_t)k * tile;
+                int64_t lo = 0, hi = nrows;
+                while (lo < hi) {
+                    const int64_t span = hi - lo;
+                    const int64_t mid = lo + span * (g + 1) / (G + 1);  // ascending in g, inside [lo, hi)
+                    int64_t c = (q < P) ? lower_bound_i32(parts[q].rowidx + c0, (int)n, (int32_t)mid) : 0;
+                    for (int d = 1; d < PP; d <<= 1) c += __shfl_xor(c, d, WAVE);
+                    const uint64_t ok = ballot(q == 0 && c >= target);
+                    if (ok) {
+                        const int gs = (__ffsll((long long)ok) - 1) / PP;  // first probe reaching the target
+                        hi = lo + span * (gs + 1) / (G + 1);
+                        if (gs > 0) lo = lo + span * gs / (G + 1) + 1;
+                    } else {
+                        lo = lo + span * G / (G + 1) + 1;
+                    }
+                }
+                if (lane() == 0) tile_row[t0 + k] = (int32_t)lo;
+            }
+            continue;
         }
         for (int k = 1; k < T; ++k) {
             const int64_t target = (int64_t)k * tile;
